@@ -1,0 +1,211 @@
+/*
+ * wdsolve -- Jacobi-preconditioned block BiCGGR for the O(a)-improved
+ * (clover) Wilson-Dirac system A X = B with L right-hand sides, on one
+ * AMD Instinct MI355X (gfx950).
+ *
+ * Problem statement (Sec. 2, eq. (1)): A is an N x N complex sparse
+ * non-Hermitian matrix with N = Lx*Ly*Lz*Lt*3*4; X and B are N x L.
+ *
+ * ---------------------------------------------------------------------------
+ * Conventions shared by every entry point
+ * ---------------------------------------------------------------------------
+ * Lattice: extents Lx, Ly, Lz, Lt (each >= 2), V = Lx*Ly*Lz*Lt sites,
+ *   site s = x + Lx*(y + Ly*(z + Lz*t)); directions mu = 0..3 are x, y, z, t.
+ *
+ * Gauge links (input of wd_set_links): complex128 (interleaved re, im)
+ *   U[mu][s][a][b], i.e. 4*V*9 complex numbers; U_mu(x) is the SU(3) link
+ *   from x to x + mu-hat.
+ *
+ * Block vectors (X, B, Y, R, Z below): N x L complex128 matrices stored
+ *   column by column; within column i the row index is n = k*V + s, where
+ *   k = 3*spin + colour (0..11) and s is the site.  Element (n, i) is at
+ *   complex offset i*N + n.  Spin refers to the chiral gamma basis below.
+ *
+ * Operator (the paper leaves the matrix to its companion paper; this is the
+ *   standard hopping-parameter form):
+ *     (A psi)(x) = T(x) psi(x)
+ *        - kappa sum_mu [ (1 - g_mu) U_mu(x) psi(x+mu)
+ *                         + (1 + g_mu) U_mu(x-mu)^dag psi(x-mu) ]
+ *     T(x) = 1 - kappa c_SW sum_{mu<nu} sigma_{mu nu} F_{mu nu}(x),
+ *     sigma_{mu nu} = (i/2)[g_mu, g_nu],
+ *     F_{mu nu}(x) = (Q_{mu nu}(x) - Q_{mu nu}(x)^dag)/(8i), Q = sum of the
+ *     four counter-clockwise plaquette leaves at x (no trace subtraction).
+ *   Gamma matrices (chiral basis, s_k Pauli): g_k = [[0, -i s_k], [i s_k, 0]]
+ *   for k = x, y, z and g_t = [[0, 1], [1, 0]]; gamma5 = diag(1, 1, -1, -1).
+ *   Boundary conditions: periodic, or antiperiodic in t (bc_t = 1).
+ *
+ * Ownership and streams: every device pointer passed in is owned by the
+ *   caller and must stay valid until the call returns; the library owns its
+ *   gauge field, clover and workspace.  All device work is issued on the
+ *   HIP stream given to wd_create and every function returns only after its
+ *   results are complete.  A context is not thread-safe.
+ *
+ * Errors: 0 is success; negative values are API or runtime errors (nothing
+ *   is modified on argument errors); positive values are numerical outcomes
+ *   of the solver, which still returns its best iterate.  No C++ exception
+ *   or abort crosses this interface.
+ */
+#ifndef WDSOLVE_H
+#define WDSOLVE_H
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct wd_ctx wd_ctx;
+
+/* return codes */
+#define WD_OK 0
+#define WD_EINVAL (-1)         /* bad argument: dims, L, null, aliasing, zero column, unknown option */
+#define WD_ENOMEM (-2)         /* device allocation failed */
+#define WD_EHIP (-3)           /* HIP runtime error */
+#define WD_ENAN (-4)           /* non-finite value met in a residual */
+#define WD_ESTATE (-5)         /* call out of order (e.g. wd_apply before wd_set_params) */
+#define WD_NOT_CONVERGED 1     /* max_iter reached */
+#define WD_BREAKDOWN 2         /* singular L x L system (rank loss) or zero step */
+#define WD_DIVERGED 3          /* max relative residual above diverge_at */
+#define WD_STAGNATED 4         /* best residual not improved for stagnate_window iterations */
+
+/* arithmetic/storage precision of an operator application */
+#define WD_F64 0
+#define WD_F32 1               /* FP32 storage of links, clover and spinors, FP32 arithmetic */
+#define WD_BF16 2              /* BF16 storage, FP32 arithmetic */
+
+/* preconditioner M of the solver */
+#define WD_PRECOND_NONE 0      /* M = I */
+#define WD_PRECOND_JACOBI 1    /* j-step Jacobi */
+#define WD_PRECOND_LEARNED 2   /* frozen linear gauge-covariant network (wd_set_learned) */
+
+/* reading of "diagonal part A_D" for the Jacobi preconditioner */
+#define WD_JACOBI_BLOCK 0      /* site-block diagonal: A_D = T(x) (12 x 12 per site) */
+#define WD_JACOBI_POINT 1      /* point diagonal: A_D = diag(T(x)) */
+
+#define WD_MAX_L 16            /* largest number of right-hand sides */
+
+/* Options of bbicggr_solve; zero-initialise and set what is needed. */
+typedef struct wd_solve_opts {
+    int j;                 /* Jacobi steps per application of M (>= 0); 0 means M = I */
+    int precond;           /* WD_PRECOND_*; NONE forces j = 0 in the cost count */
+    int prec_inner;        /* WD_F64 / WD_F32 / WD_BF16 storage of the Jacobi preconditioner */
+    int use_x0;            /* 1: X holds the initial guess; 0: start from X = 0 */
+    int max_iter;          /* outer iterations per run; <= 0 means 5000 */
+    int max_restarts;      /* true-residual restarts; < 0 means 3 */
+    int stagnate_window;   /* <= 0 means 200 */
+    double diverge_at;     /* <= 0 means 1e2 */
+    double* history;       /* optional host buffer: max relative recursive residual per iteration */
+    int history_len;       /* its length in doubles */
+} wd_solve_opts;
+
+/* Results of bbicggr_solve. */
+typedef struct wd_solve_info {
+    int status;                        /* WD_OK or a positive outcome code */
+    int iterations;                    /* outer iterations of the last run */
+    int total_iterations;              /* over all restarts */
+    int restarts;                      /* true-residual restarts made */
+    long long mvm_paper;               /* per column, counted as in Table 1: 2(j+1)k + 1 per run */
+    long long mvm_actual;              /* per column: hopping-term applications actually made */
+    double seconds;                    /* wall time of the solve (device synchronised) */
+    double bytes_alg;                  /* algorithmic HBM bytes of every kernel launched by the solve */
+    double true_residual[WD_MAX_L];    /* ||b - A x|| / ||b|| per column, FP64 */
+    double recursive_residual[WD_MAX_L];
+} wd_solve_info;
+
+/* ---------------------------------------------------------------------------
+ * Setup
+ * ------------------------------------------------------------------------- */
+
+/* Create a context for an Lx x Ly x Lz x Lt lattice (dims[0..3] = Lx, Ly,
+ * Lz, Lt, each >= 2) with up to max_L right-hand sides (1..WD_MAX_L).
+ * bc_t: 0 periodic, 1 antiperiodic in t.  hip_stream: a hipStream_t (NULL
+ * for the default stream).  Workspace for max_L columns is allocated here.
+ * Errors: WD_EINVAL, WD_ENOMEM, WD_EHIP. */
+int wd_create(wd_ctx** out, const int dims[4], int bc_t, int max_L, void* hip_stream);
+
+/* Release the context and all library-owned device memory. */
+int wd_destroy(wd_ctx* ctx);
+
+/* Load the gauge field U[mu][s][a][b] (complex128, layout above); U is a
+ * host pointer when on_device == 0, a device pointer otherwise.  The links
+ * are copied; the caller's buffer is not kept. */
+int wd_set_links(wd_ctx* ctx, const double* U, int on_device);
+
+/* Set kappa and c_SW and build, on the GPU, the clover field strength, the
+ * site matrices T(x) = T_+ (+) T_- (two 6 x 6 Hermitian chiral blocks) and
+ * their inverses in FP64, plus FP32 and BF16 copies for the low-precision
+ * preconditioner.  jacobi_kind: WD_JACOBI_BLOCK or WD_JACOBI_POINT (the
+ * reading of A_D in Sec. 2's Jacobi preconditioner).  Needs wd_set_links. */
+int wd_set_params(wd_ctx* ctx, double kappa, double csw, int jacobi_kind);
+
+/* Copy the site matrices to host memory: which = 0 gives T, 1 gives T^{-1}.
+ * out receives V*2*36 complex128: [s][chirality c][row][col] of the 6 x 6
+ * block acting on spins (2c, 2c+1) x colours, row/col index 3*spin' + colour
+ * with spin' = spin - 2c. */
+int wd_get_clover(wd_ctx* ctx, int which, double* out_host);
+
+/* ---------------------------------------------------------------------------
+ * The hot path
+ * ------------------------------------------------------------------------- */
+
+/* Y = A X for L columns (1 <= L <= max_L).  X and Y are device pointers to
+ * N x L block vectors and must not overlap.  prec selects the storage and
+ * arithmetic precision of the application (WD_F64 for results at full
+ * accuracy; WD_F32 / WD_BF16 round X, the links and the clover to that
+ * format and accumulate in FP32; Y is always written in FP64). */
+int wd_apply(wd_ctx* ctx, const void* X, void* Y, int L, int prec);
+
+/* Z = M R with M the j-step Jacobi preconditioner of Sec. 2 (the display
+ * after the algorithm box) with initial guess G_0 = 0:
+ *   Z = sum_{i=0}^{j-1} (I - A_D^{-1} A)^i A_D^{-1} R  (j >= 1),  Z = R (j = 0),
+ * evaluated as j sweeps Z_{i+1} = Z_i + A_D^{-1}(R - A Z_i).  prec selects the
+ * storage of links, clover and the iterates (FP64, FP32 or BF16 with FP32
+ * accumulation); R and Z are FP64 device block vectors and must not overlap. */
+int jacobi_precond(wd_ctx* ctx, const void* R, void* Z, int L, int j, int prec);
+
+/* Solve A X = B with preconditioned block BiCGGR (Sec. 2, algorithm box)
+ * with Rt_0 = R_0 (Sec. 3.3), stopping when the largest relative recursive
+ * residual max_i ||r^(i)|| / ||b^(i)|| falls to tol; the FP64 true residual is
+ * then recomputed and the solver restarts from the current X while any
+ * column's true residual exceeds tol (up to max_restarts times).  B and X are
+ * device block vectors (X in/out); opts may be NULL (defaults, j = 0); info
+ * may be NULL.  Every column of B must be non-zero.
+ * Returns WD_OK, a positive outcome code, or a negative error. */
+int bbicggr_solve(wd_ctx* ctx, const void* B, void* X, int L, double tol,
+                  const wd_solve_opts* opts, wd_solve_info* info);
+
+/* Throughput measurement: launch the hopping kernel nrep times back to back
+ * on the context stream, then wait.  mode 0 is Y = A X (as wd_apply);
+ * mode 1 is one Jacobi sweep Y = A_D^{-1} (R + kappa H X) (the kernel that
+ * jacobi_precond runs j - 1 times).  X, R, Y: device block vectors of L
+ * columns in FP64 (prec must be WD_F64 here); R is ignored for mode 0. */
+int wd_hop_repeat(wd_ctx* ctx, const void* X, const void* R, void* Y, int L, int mode, int prec, int nrep);
+
+/* ---------------------------------------------------------------------------
+ * Block kernels of the outer iteration, exposed for testing
+ * ------------------------------------------------------------------------- */
+
+/* C = P^H Q (L x L, complex128, row-major: C[i*L + j] = sum_n conj(P[n,i]) Q[n,j])
+ * for device block vectors P, Q of L columns; C is a device pointer.  This is
+ * the tall-skinny product behind Rt_0^H V_k and Rt_0^H R_k (Sec. 2). */
+int wd_block_gram(wd_ctx* ctx, const void* P, const void* Q, int L, void* C);
+
+/* Solve M Z = RHS for L x L complex128 row-major device matrices by LU with
+ * partial pivoting in FP64 on the GPU (the alpha and gamma systems of
+ * Sec. 2).  Returns WD_BREAKDOWN if a pivot is below 1e-14 max|M| or M is
+ * not finite. */
+int wd_small_solve(wd_ctx* ctx, const void* M, const void* RHS, int L, void* Z);
+
+/* ---------------------------------------------------------------------------
+ * Utilities
+ * ------------------------------------------------------------------------- */
+
+/* Static text for a return code. */
+const char* wd_strerror(int code);
+
+/* Lattice volume and N of a context. */
+long long wd_volume(const wd_ctx* ctx);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* WDSOLVE_H */

@@ -223,3 +223,97 @@ class WilsonClover:
 
     def point_index(self, site: int, spin: int, colour: int) -> int:
         return 12 * site + 3 * spin + colour
+
+
+# --------------------------------------------------------------------------
+# Single-site evaluation (for spot checks on lattices too large for the
+# whole-lattice arrays above)
+# --------------------------------------------------------------------------
+
+class SiteOperator:
+    """(A psi)(x) at individual sites, from the links around x only.
+
+    Same definition as ``WilsonClover`` written site by site with explicit
+    coordinates: the clover leaves at x are multiplied out link by link and
+    the eight hops gather psi from the neighbours of x.  ``links_abi`` is the
+    (4, V, 3, 3) exchange array; psi is read through ``get_spinor(site)``
+    returning a (12, L) array (row 3*spin + colour).
+    """
+
+    def __init__(self, dims, links_abi, kappa, csw, bc_t=0):
+        self.dims = tuple(int(d) for d in dims)
+        self.U = links_abi
+        self.kappa = float(kappa)
+        self.csw = float(csw)
+        self.bc_t = int(bc_t)
+        self.g = gammas()
+
+    def site(self, c):
+        lx, ly, lz, lt = self.dims
+        return (c[0] % lx) + lx * ((c[1] % ly) + ly * ((c[2] % lz) + lz * (c[3] % lt)))
+
+    def coords(self, s):
+        lx, ly, lz, lt = self.dims
+        return [s % lx, (s // lx) % ly, (s // (lx * ly)) % lz, s // (lx * ly * lz)]
+
+    def link(self, mu, c):
+        return self.U[mu, self.site(c)]
+
+    @staticmethod
+    def _mv(c, mu, d):
+        c = list(c)
+        c[mu] += d
+        return c
+
+    def field_strength(self, c, mu, nu):
+        H = dag
+        mv = self._mv
+        lk = self.link
+        l1 = lk(mu, c) @ lk(nu, mv(c, mu, 1)) @ H(lk(mu, mv(c, nu, 1))) @ H(lk(nu, c))
+        l2 = lk(nu, c) @ H(lk(mu, mv(mv(c, mu, -1), nu, 1))) @ H(lk(nu, mv(c, mu, -1))) @ lk(mu, mv(c, mu, -1))
+        l3 = H(lk(mu, mv(c, mu, -1))) @ H(lk(nu, mv(mv(c, mu, -1), nu, -1))) \
+            @ lk(mu, mv(mv(c, mu, -1), nu, -1)) @ lk(nu, mv(c, nu, -1))
+        l4 = H(lk(nu, mv(c, nu, -1))) @ lk(mu, mv(c, nu, -1)) @ lk(nu, mv(mv(c, mu, 1), nu, -1)) @ H(lk(mu, c))
+        Q = l1 + l2 + l3 + l4
+        return (Q - dag(Q)) / 8j
+
+    def T(self, s):
+        c = self.coords(s)
+        T = np.eye(12, dtype=np.complex128)
+        for mu in range(4):
+            for nu in range(mu + 1, 4):
+                T -= self.kappa * self.csw * np.kron(sigma_munu(mu, nu), self.field_strength(c, mu, nu))
+        return T
+
+    def neighbours(self, s):
+        """[(mu, +1/-1, neighbour site, boundary sign)] for the eight hops of s."""
+        c = self.coords(s)
+        out = []
+        lt = self.dims[3]
+        for mu in range(4):
+            for d in (1, -1):
+                cn = self._mv(c, mu, d)
+                sign = 1.0
+                if self.bc_t and mu == 3 and (cn[3] == lt or cn[3] == -1):
+                    sign = -1.0
+                out.append((mu, d, self.site(cn), sign))
+        return out
+
+    def hop_at(self, s, get_spinor):
+        """(H psi)(x) at site s, shape (12, L)."""
+        c = self.coords(s)
+        acc = None
+        one = np.eye(4)
+        for mu, d, sn, sign in self.neighbours(s):
+            psi = get_spinor(sn)
+            if d == 1:
+                M = np.kron(one - self.g[mu], self.link(mu, c))
+            else:
+                M = np.kron(one + self.g[mu], dag(self.link(mu, self._mv(c, mu, -1))))
+            term = sign * (M @ psi)
+            acc = term if acc is None else acc + term
+        return acc
+
+    def apply_at(self, s, get_spinor):
+        """(A psi)(x) at site s, shape (12, L)."""
+        return self.T(s) @ get_spinor(s) - self.kappa * self.hop_at(s, get_spinor)

@@ -1,0 +1,588 @@
+// C ABI of the wdsolve library: context, setup, operator, preconditioner and
+// the preconditioned block BiCGGR driver (Sec. 2, algorithm box; Sec. 3.3
+// for the initial choices and the stopping rule).
+#include <chrono>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <vector>
+
+#include "wd_internal.h"
+
+using namespace wd;
+
+namespace {
+
+#define WD_TRY_HIP(expr)                           \
+    do {                                           \
+        hipError_t e_ = (expr);                    \
+        if (e_ != hipSuccess) return WD_EHIP;      \
+    } while (0)
+
+size_t block_elems(const wd_ctx* c, int L) { return (size_t)12 * c->g.V * L; }
+
+bool overlap(const void* a, const void* b, size_t bytes) {
+    const char* pa = (const char*)a;
+    const char* pb = (const char*)b;
+    return pa < pb + bytes && pb < pa + bytes;
+}
+
+int dev_alloc(void** p, size_t bytes) {
+    if (hipMalloc(p, bytes) != hipSuccess) {
+        *p = nullptr;
+        (void)hipGetLastError();
+        return WD_ENOMEM;
+    }
+    return WD_OK;
+}
+
+void dev_free(void*& p) {
+    if (p) (void)hipFree(p);
+    p = nullptr;
+}
+
+// Workspace roles in ctx->ws
+enum { WS_R = 0, WS_RT, WS_P, WS_V, WS_W, WS_F, WS_G, WS_U, WS_Y, WS_T1, WS_JT = 10, WS_T2 = 11 };
+
+// Small device control block (after the L x L matrices in ctx->small)
+struct Ctl {
+    double norms[WD_MAX_L];
+    int status;
+    int pad;
+};
+
+struct SmallLayout {
+    double2 *C_r, *C_rn, *alpha, *gamma, *zeta;
+    Ctl* ctl;
+};
+
+SmallLayout small_layout(wd_ctx* c) {
+    SmallLayout s;
+    s.C_r = c->small;
+    s.C_rn = c->small + 256;
+    s.alpha = c->small + 512;
+    s.gamma = c->small + 768;
+    s.zeta = c->small + 1024;
+    s.ctl = reinterpret_cast<Ctl*>(c->small + 1032);
+    return s;
+}
+constexpr size_t kSmallPairs = 1032 + (sizeof(Ctl) + 15) / 16 + 1;
+
+int lowp_ensure(wd_ctx* c) {
+    if (c->lp[0]) return WD_OK;
+    const size_t bytes = block_elems(c, c->max_L) * sizeof(float2);
+    for (int i = 0; i < 3; ++i) {
+        int r = dev_alloc(&c->lp[i], bytes);
+        if (r != WD_OK) return r;
+    }
+    return WD_OK;
+}
+
+int check_prec(int prec) { return (prec == WD_F64 || prec == WD_F32 || prec == WD_BF16) ? WD_OK : WD_EINVAL; }
+
+// host copy of the squared column norms of an N x L block
+int colnorms_host(wd_ctx* c, const double2* R, int L, double* out) {
+    const size_t N = (size_t)12 * c->g.V;
+    const int nb = gram_blocks(N);
+    SmallLayout s = small_layout(c);
+    WD_TRY_HIP(launch_colnorms(R, N, L, c->partial, nb, s.ctl->norms, c->stream));
+    WD_TRY_HIP(hipMemcpyAsync(out, s.ctl->norms, sizeof(double) * L, hipMemcpyDeviceToHost, c->stream));
+    WD_TRY_HIP(hipStreamSynchronize(c->stream));
+    return WD_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* wd_strerror(int code) {
+    switch (code) {
+        case WD_OK: return "ok";
+        case WD_EINVAL: return "invalid argument";
+        case WD_ENOMEM: return "device allocation failed";
+        case WD_EHIP: return "HIP runtime error";
+        case WD_ENAN: return "non-finite value in a residual";
+        case WD_ESTATE: return "call out of order (links or parameters not set)";
+        case WD_NOT_CONVERGED: return "not converged within max_iter";
+        case WD_BREAKDOWN: return "breakdown: singular L x L system or zero step";
+        case WD_DIVERGED: return "diverged: residual above diverge_at";
+        case WD_STAGNATED: return "stagnated: no improvement within stagnate_window";
+        default: return "unknown code";
+    }
+}
+
+long long wd_volume(const wd_ctx* c) { return c ? (long long)c->g.V : -1; }
+
+int wd_destroy(wd_ctx* c) {
+    if (!c) return WD_EINVAL;
+    dev_free((void*&)c->f.U);
+    dev_free((void*&)c->f.T);
+    for (int p = 0; p < 3; ++p) {
+        dev_free(c->f.Uk[p]);
+        dev_free(c->f.Ti[p]);
+        dev_free(c->f.Tp[p]);
+        dev_free(c->f.Tc[p]);
+    }
+    for (auto& w : c->ws) dev_free((void*&)w);
+    for (auto& w : c->lp) dev_free(w);
+    dev_free((void*&)c->partial);
+    dev_free((void*&)c->small);
+    dev_free((void*&)c->theta);
+    if (c->host_ctl) (void)hipHostFree(c->host_ctl);
+    delete c;
+    return WD_OK;
+}
+
+int wd_create(wd_ctx** out, const int dims[4], int bc_t, int max_L, void* hip_stream) {
+    if (!out || !dims) return WD_EINVAL;
+    *out = nullptr;
+    for (int m = 0; m < 4; ++m)
+        if (dims[m] < 2) return WD_EINVAL;
+    if (bc_t != 0 && bc_t != 1) return WD_EINVAL;
+    if (max_L < 1 || max_L > WD_MAX_L) return WD_EINVAL;
+    const long long V = (long long)dims[0] * dims[1] * dims[2] * dims[3];
+    if (V > (1LL << 31) - 1) return WD_EINVAL;  // site indices are 32-bit
+    wd_ctx* c = new (std::nothrow) wd_ctx();
+    if (!c) return WD_ENOMEM;
+    c->g.lx = dims[0];
+    c->g.ly = dims[1];
+    c->g.lz = dims[2];
+    c->g.lt = dims[3];
+    c->g.V = (int)V;
+    c->g.sxy = dims[0] * dims[1];
+    c->g.sxyz = dims[0] * dims[1] * dims[2];
+    c->bc_t = bc_t;
+    c->max_L = max_L;
+    c->stream = (hipStream_t)hip_stream;
+    int r = WD_OK;
+    const size_t links = (size_t)4 * 9 * V, clov = (size_t)2 * 18 * V;
+    r = r ? r : dev_alloc((void**)&c->f.U, links * 16);
+    r = r ? r : dev_alloc((void**)&c->f.T, clov * 16);
+    const size_t psz[3] = {16, 8, 4};
+    for (int p = 0; p < 3 && !r; ++p) {
+        r = r ? r : dev_alloc(&c->f.Uk[p], links * psz[p]);
+        r = r ? r : dev_alloc(&c->f.Ti[p], clov * psz[p]);
+        r = r ? r : dev_alloc(&c->f.Tp[p], clov * psz[p]);
+        r = r ? r : dev_alloc(&c->f.Tc[p], clov * psz[p]);
+    }
+    for (auto& w : c->ws) r = r ? r : dev_alloc((void**)&w, block_elems(c, max_L) * 16);
+    r = r ? r : dev_alloc((void**)&c->partial, (size_t)512 * partial_stride() * 16);
+    r = r ? r : dev_alloc((void**)&c->small, kSmallPairs * 16);
+    if (!r && hipHostMalloc((void**)&c->host_ctl, sizeof(Ctl)) != hipSuccess) r = WD_ENOMEM;
+    if (r) {
+        wd_destroy(c);
+        return r;
+    }
+    *out = c;
+    return WD_OK;
+}
+
+int wd_set_links(wd_ctx* c, const double* U, int on_device) {
+    if (!c || !U) return WD_EINVAL;
+    const size_t n = (size_t)4 * 9 * c->g.V;
+    const double2* src = (const double2*)U;
+    void* staging = nullptr;
+    if (!on_device) {
+        // stage through the T2 workspace block (large enough: 36 V <= 12 V max_L only if
+        // max_L >= 3), otherwise through a temporary allocation
+        if (n <= block_elems(c, c->max_L)) {
+            staging = c->ws[WS_T2];
+        } else {
+            int r = dev_alloc(&staging, n * 16);
+            if (r) return r;
+        }
+        if (hipMemcpyAsync(staging, U, n * 16, hipMemcpyHostToDevice, c->stream) != hipSuccess) {
+            if (staging != c->ws[WS_T2]) dev_free(staging);
+            return WD_EHIP;
+        }
+        src = (const double2*)staging;
+    }
+    hipError_t e = launch_links_from_abi(src, c->f.U, c->g, c->bc_t, c->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+    if (staging && staging != c->ws[WS_T2]) dev_free(staging);
+    if (e != hipSuccess) return WD_EHIP;
+    c->have_links = true;
+    c->have_params = false;
+    return WD_OK;
+}
+
+int wd_set_params(wd_ctx* c, double kappa, double csw, int jacobi_kind) {
+    if (!c) return WD_EINVAL;
+    if (!c->have_links) return WD_ESTATE;
+    if (!std::isfinite(kappa) || !std::isfinite(csw)) return WD_EINVAL;
+    if (jacobi_kind != WD_JACOBI_BLOCK && jacobi_kind != WD_JACOBI_POINT) return WD_EINVAL;
+    const size_t V = c->g.V, links = (size_t)36 * V, clov = (size_t)36 * V;
+    hipStream_t s = c->stream;
+    double2* Ti64 = (double2*)c->f.Ti[0];
+    WD_TRY_HIP(launch_clover(c->f.U, c->f.T, Ti64, c->g, kappa, csw, s));
+    WD_TRY_HIP(launch_point_form(c->f.T, (double2*)c->f.Tp[0], V, s));
+    WD_TRY_HIP(launch_convert(c->f.U, c->f.Uk[0], Prec::F64, kappa, links, s));
+    WD_TRY_HIP(launch_convert(c->f.T, c->f.Tc[0], Prec::F64, 1.0, clov, s));
+    for (int p = 1; p < 3; ++p) {
+        const Prec pr = (Prec)p;
+        WD_TRY_HIP(launch_convert(c->f.U, c->f.Uk[p], pr, kappa, links, s));
+        WD_TRY_HIP(launch_convert(Ti64, c->f.Ti[p], pr, 1.0, clov, s));
+        WD_TRY_HIP(launch_convert((const double2*)c->f.Tp[0], c->f.Tp[p], pr, 1.0, clov, s));
+        WD_TRY_HIP(launch_convert(c->f.T, c->f.Tc[p], pr, 1.0, clov, s));
+    }
+    WD_TRY_HIP(hipStreamSynchronize(s));
+    c->kappa = kappa;
+    c->csw = csw;
+    c->jacobi_kind = jacobi_kind;
+    c->have_params = true;
+    return WD_OK;
+}
+
+int wd_get_clover(wd_ctx* c, int which, double* out_host) {
+    if (!c || !out_host || (which != 0 && which != 1)) return WD_EINVAL;
+    if (!c->have_params) return WD_ESTATE;
+    const size_t V = c->g.V;
+    std::vector<double2> packed(36 * V);
+    const void* src = which == 0 ? (const void*)c->f.T : c->f.Ti[0];
+    WD_TRY_HIP(hipMemcpyAsync(packed.data(), src, 36 * V * 16, hipMemcpyDeviceToHost, c->stream));
+    WD_TRY_HIP(hipStreamSynchronize(c->stream));
+    double2* out = (double2*)out_host;
+    for (size_t s = 0; s < V; ++s)
+        for (int ch = 0; ch < 2; ++ch) {
+            double2* m = out + (s * 2 + ch) * 36;
+            for (int i = 0; i < 3; ++i) {
+                const double2 d = packed[(ch * 18 + i) * V + s];
+                m[(2 * i) * 6 + 2 * i] = make_double2(d.x, 0.0);
+                m[(2 * i + 1) * 6 + 2 * i + 1] = make_double2(d.y, 0.0);
+            }
+            for (int i = 0; i < 6; ++i)
+                for (int j = i + 1; j < 6; ++j) {
+                    const double2 o = packed[(ch * 18 + 3 + herm_index(i, j)) * V + s];
+                    m[i * 6 + j] = o;
+                    m[j * 6 + i] = make_double2(o.x, -o.y);
+                }
+        }
+    return WD_OK;
+}
+
+int wd_apply(wd_ctx* c, const void* X, void* Y, int L, int prec) {
+    if (!c || !X || !Y) return WD_EINVAL;
+    if (L < 1 || L > c->max_L || check_prec(prec)) return WD_EINVAL;
+    if (!c->have_params) return WD_ESTATE;
+    if (overlap(X, Y, block_elems(c, L) * 16)) return WD_EINVAL;
+    if (prec == WD_F64) {
+        WD_TRY_HIP(launch_apply_A(c, (const double2*)X, (double2*)Y, L, c->stream));
+    } else {
+        int r = lowp_ensure(c);
+        if (r) return r;
+        WD_TRY_HIP(launch_apply_A_lowp(c, (const double2*)X, (double2*)Y, L, (Prec)prec, c->stream));
+    }
+    WD_TRY_HIP(hipStreamSynchronize(c->stream));
+    return WD_OK;
+}
+
+int jacobi_precond(wd_ctx* c, const void* R, void* Z, int L, int j, int prec) {
+    if (!c || !R || !Z) return WD_EINVAL;
+    if (L < 1 || L > c->max_L || j < 0 || check_prec(prec)) return WD_EINVAL;
+    if (!c->have_params) return WD_ESTATE;
+    if (overlap(R, Z, block_elems(c, L) * 16)) return WD_EINVAL;
+    if (prec != WD_F64) {
+        int r = lowp_ensure(c);
+        if (r) return r;
+    }
+    WD_TRY_HIP(launch_jacobi(c, (const double2*)R, (double2*)Z, L, j, (Prec)prec, c->stream));
+    WD_TRY_HIP(hipStreamSynchronize(c->stream));
+    return WD_OK;
+}
+
+int wd_hop_repeat(wd_ctx* c, const void* X, const void* R, void* Y, int L, int mode, int prec, int nrep) {
+    if (!c || !X || !Y || (mode == 1 && !R)) return WD_EINVAL;
+    if (L < 1 || L > c->max_L || prec != WD_F64 || nrep < 1 || (mode != 0 && mode != 1)) return WD_EINVAL;
+    if (!c->have_params) return WD_ESTATE;
+    const size_t bytes = block_elems(c, L) * 16;
+    if (overlap(X, Y, bytes) || (mode == 1 && overlap(R, Y, bytes))) return WD_EINVAL;
+    for (int i = 0; i < nrep; ++i) {
+        if (mode == 0)
+            WD_TRY_HIP(launch_apply_A(c, (const double2*)X, (double2*)Y, L, c->stream));
+        else
+            WD_TRY_HIP(launch_sweep_f64(c, (const double2*)X, (const double2*)R, (double2*)Y, L, c->stream));
+    }
+    WD_TRY_HIP(hipStreamSynchronize(c->stream));
+    return WD_OK;
+}
+
+int wd_block_gram(wd_ctx* c, const void* P, const void* Q, int L, void* C) {
+    if (!c || !P || !Q || !C) return WD_EINVAL;
+    if (L < 1 || L > c->max_L) return WD_EINVAL;
+    const size_t N = (size_t)12 * c->g.V;
+    const int nb = gram_blocks(N);
+    WD_TRY_HIP(launch_gram_partials((const double2*)P, (const double2*)Q, N, L, c->partial, nb, c->stream));
+    WD_TRY_HIP(launch_reduce_gram(c->partial, nb, L, (double2*)C, c->stream));
+    WD_TRY_HIP(hipStreamSynchronize(c->stream));
+    return WD_OK;
+}
+
+int wd_small_solve(wd_ctx* c, const void* M, const void* RHS, int L, void* Z) {
+    if (!c || !M || !RHS || !Z) return WD_EINVAL;
+    if (L < 1 || L > WD_MAX_L) return WD_EINVAL;
+    SmallLayout s = small_layout(c);
+    WD_TRY_HIP(launch_small_solve((const double2*)M, (const double2*)RHS, L, (double2*)Z, &s.ctl->status,
+                                  c->stream));
+    int st = 0;
+    WD_TRY_HIP(hipMemcpyAsync(&st, &s.ctl->status, sizeof(int), hipMemcpyDeviceToHost, c->stream));
+    WD_TRY_HIP(hipStreamSynchronize(c->stream));
+    return st ? WD_BREAKDOWN : WD_OK;
+}
+
+// ---------------------------------------------------------------------------
+// Preconditioned block BiCGGR
+// ---------------------------------------------------------------------------
+namespace {
+
+struct Solver {
+    wd_ctx* c;
+    int L;
+    size_t N;
+    int nb;
+    int j;
+    int precond;
+    Prec pin;
+    SmallLayout sl;
+    SolverBufs bufs;
+    long long mvm_paper = 0, mvm_actual = 0;
+    double bytes = 0.0;  // algorithmic HBM bytes of the launched kernels
+
+    double2* ws(int i) { return c->ws[i]; }
+    // one pass over n N x L blocks
+    void blocks(double n) { bytes += n * 192.0 * L * c->g.V; }
+
+    int applyM(const double2* in, double2* out) {
+        if (precond == WD_PRECOND_JACOBI && j > 0) {
+            WD_TRY_HIP(launch_jacobi(c, in, out, L, j, pin, c->stream));
+            mvm_actual += j - 1;
+            const double scale = pin == Prec::F64 ? 1.0 : (pin == Prec::F32 ? 0.5 : 0.25);
+            bytes += (double)c->g.V * (bytes_first_sweep(L) + (j - 1) * bytes_sweep(L)) * scale;
+        } else {
+            WD_TRY_HIP(launch_copy(out, in, N * L, c->stream));
+            blocks(2);
+        }
+        mvm_paper += j;
+        return WD_OK;
+    }
+    int applyA(const double2* in, double2* out) {
+        WD_TRY_HIP(launch_apply_A(c, in, out, L, c->stream));
+        mvm_paper += 1;
+        mvm_actual += 1;
+        bytes += (double)c->g.V * bytes_apply(L);
+        return WD_OK;
+    }
+    int gram_into(const double2* P, const double2* Q, double2* C) {
+        WD_TRY_HIP(launch_gram_partials(P, Q, N, L, c->partial, nb, c->stream));
+        WD_TRY_HIP(launch_reduce_gram(c->partial, nb, L, C, c->stream));
+        return WD_OK;
+    }
+    int fetch_ctl(Ctl* h) {
+        WD_TRY_HIP(hipMemcpyAsync(h, sl.ctl, sizeof(Ctl), hipMemcpyDeviceToHost, c->stream));
+        WD_TRY_HIP(hipStreamSynchronize(c->stream));
+        return WD_OK;
+    }
+};
+
+}  // namespace
+
+int bbicggr_solve(wd_ctx* c, const void* Bv, void* Xv, int L, double tol, const wd_solve_opts* o,
+                  wd_solve_info* info) {
+    if (!c || !Bv || !Xv) return WD_EINVAL;
+    if (L < 1 || L > c->max_L || !(tol > 0.0)) return WD_EINVAL;
+    if (!c->have_params) return WD_ESTATE;
+    wd_solve_opts op{};
+    if (o) op = *o;
+    if (op.precond != WD_PRECOND_NONE && op.precond != WD_PRECOND_JACOBI) return WD_EINVAL;
+    if (op.j < 0 || check_prec(op.prec_inner)) return WD_EINVAL;
+    if (op.precond == WD_PRECOND_NONE) op.j = 0;
+    const int max_iter = op.max_iter > 0 ? op.max_iter : 5000;
+    const int max_restarts = op.max_restarts >= 0 ? op.max_restarts : 3;
+    const int stag = op.stagnate_window > 0 ? op.stagnate_window : 200;
+    const double diverge_at = op.diverge_at > 0 ? op.diverge_at : 1e2;
+    const size_t N = (size_t)12 * c->g.V;
+    if (overlap(Bv, Xv, N * L * 16)) return WD_EINVAL;
+    if (op.prec_inner != WD_F64 && op.precond == WD_PRECOND_JACOBI) {
+        int r = lowp_ensure(c);
+        if (r) return r;
+    }
+
+    Solver S;
+    S.c = c;
+    S.L = L;
+    S.N = N;
+    S.nb = gram_blocks(N);
+    S.j = op.j;
+    S.precond = op.precond;
+    S.pin = (Prec)op.prec_inner;
+    S.sl = small_layout(c);
+    S.bufs = SolverBufs{S.sl.C_r, S.sl.C_rn, S.sl.alpha, S.sl.gamma, S.sl.zeta, S.sl.ctl->norms,
+                        &S.sl.ctl->status};
+    hipStream_t st = c->stream;
+    const double2* B = (const double2*)Bv;
+    double2* X = (double2*)Xv;
+    double2 *R = S.ws(WS_R), *Rt = S.ws(WS_RT), *P = S.ws(WS_P), *V = S.ws(WS_V), *W = S.ws(WS_W),
+            *F = S.ws(WS_F), *G = S.ws(WS_G), *U = S.ws(WS_U), *Y = S.ws(WS_Y), *T1 = S.ws(WS_T1);
+
+    WD_TRY_HIP(hipStreamSynchronize(st));
+    const auto t0 = std::chrono::steady_clock::now();
+
+    double bn2[WD_MAX_L];
+    int r = colnorms_host(c, B, L, bn2);
+    if (r) return r;
+    double bnorm[WD_MAX_L];
+    for (int i = 0; i < L; ++i) {
+        if (!std::isfinite(bn2[i])) return WD_ENAN;
+        if (bn2[i] == 0.0) return WD_EINVAL;
+        bnorm[i] = std::sqrt(bn2[i]);
+    }
+
+    Ctl* hc = reinterpret_cast<Ctl*>(c->host_ctl);
+    int status = WD_NOT_CONVERGED;
+    int iters = 0, total_iters = 0, restarts = 0, hist_pos = 0;
+    bool use_x0 = op.use_x0 != 0;
+    double true_rel[WD_MAX_L] = {0}, rec_rel[WD_MAX_L] = {0};
+
+    auto record = [&](double v) {
+        if (op.history && hist_pos < op.history_len) op.history[hist_pos] = v;
+        ++hist_pos;
+    };
+
+    for (;;) {
+        // ---- initialisation: R0 = B - A X0, P0 = R0, Rt0 = R0, F0 = M R0, V0 = W0 = A F0
+        if (use_x0) {
+            if ((r = S.applyA(X, T1))) return r;
+            WD_TRY_HIP(launch_axpby_block(B, T1, R, N * L, st));
+        } else {
+            WD_TRY_HIP(launch_zero(X, N * L, st));
+            WD_TRY_HIP(launch_copy(R, B, N * L, st));
+            S.mvm_paper += 1;  // R0 = B - A X0 counts as one application (Table 1 convention)
+        }
+        WD_TRY_HIP(launch_copy(P, R, N * L, st));
+        WD_TRY_HIP(launch_copy(Rt, R, N * L, st));
+        if ((r = S.applyM(R, F))) return r;
+        if ((r = S.applyA(F, W))) return r;
+        WD_TRY_HIP(launch_copy(V, W, N * L, st));
+        if ((r = S.gram_into(Rt, R, S.sl.C_r))) return r;
+        WD_TRY_HIP(launch_zero(reinterpret_cast<double2*>(S.sl.ctl), (sizeof(Ctl) + 15) / 16, st));
+        double rn2[WD_MAX_L];
+        if ((r = colnorms_host(c, R, L, rn2))) return r;
+        double res = 0.0;
+        for (int i = 0; i < L; ++i) {
+            rec_rel[i] = std::sqrt(rn2[i]) / bnorm[i];
+            res = std::fmax(res, rec_rel[i]);
+        }
+        if (!std::isfinite(res)) {
+            status = WD_ENAN;
+            break;
+        }
+        record(res);
+        iters = 0;
+        int run_status = WD_NOT_CONVERGED;
+        double best = res;
+        int best_k = 0;
+        if (res <= tol) run_status = WD_OK;
+        for (int k = 0; run_status == WD_NOT_CONVERGED && k < max_iter; ++k) {
+            // alpha and zeta
+            WD_TRY_HIP(launch_gram1(Rt, V, W, R, N, L, c->partial, S.nb, st));
+            WD_TRY_HIP(launch_solve_alpha(c->partial, S.nb, L, S.bufs, st));
+            // U = (P - zeta V) alpha ; G = M U ; Y = A G
+            WD_TRY_HIP(launch_update_U(P, V, S.sl.zeta, S.sl.alpha, U, N, L, st));
+            S.blocks(4 + 3 + 9);
+            const long long mp = S.mvm_paper, ma = S.mvm_actual;
+            if ((r = S.applyM(U, G))) return r;
+            if ((r = S.applyA(G, Y))) return r;
+            // X += zeta F + G ; R -= zeta W + Y ; Rt^H R_{k+1}, norms ; gamma
+            WD_TRY_HIP(launch_update_XR(X, R, F, G, W, Y, Rt, S.sl.zeta, N, L, c->partial, S.nb, st));
+            WD_TRY_HIP(launch_solve_gamma(c->partial, S.nb, L, S.bufs, st));
+            if ((r = S.fetch_ctl(hc))) return r;
+            if (hc->status & 1) {  // alpha system singular: X and R were left unchanged
+                S.mvm_paper = mp;
+                S.mvm_actual = ma;
+                run_status = WD_BREAKDOWN;
+                break;
+            }
+            iters = k + 1;
+            res = 0.0;
+            bool nan = (hc->status & 4) != 0;
+            for (int i = 0; i < L; ++i) {
+                rec_rel[i] = std::sqrt(hc->norms[i]) / bnorm[i];
+                if (!std::isfinite(rec_rel[i])) nan = true;
+                res = std::fmax(res, rec_rel[i]);
+            }
+            record(res);
+            if (nan) {
+                run_status = WD_ENAN;
+                break;
+            }
+            if (res <= tol) {
+                run_status = WD_OK;
+                break;
+            }
+            if (res > diverge_at) {
+                run_status = WD_DIVERGED;
+                break;
+            }
+            if (res < best) {
+                best = res;
+                best_k = k + 1;
+            } else if (k + 1 - best_k >= stag) {
+                run_status = WD_STAGNATED;
+                break;
+            }
+            // F = M R_{k+1} ; W = A F
+            if ((r = S.applyM(R, F))) return r;
+            if ((r = S.applyA(F, W))) return r;
+            if (hc->status & 2) {
+                run_status = WD_BREAKDOWN;
+                break;
+            }
+            // P = R + U gamma ; V = W + Y gamma
+            WD_TRY_HIP(launch_update_PV(P, V, R, W, U, Y, S.sl.gamma, N, L, st));
+            S.blocks(6);
+        }
+        total_iters += iters;
+        status = run_status;
+        if (status == WD_ENAN) break;
+        // ---- true residual ||B - A X|| / ||B|| in FP64
+        WD_TRY_HIP(launch_apply_A(c, X, T1, L, st));
+        S.mvm_actual += 1;
+        WD_TRY_HIP(launch_axpby_block(B, T1, T1, N * L, st));
+        double tr2[WD_MAX_L];
+        if ((r = colnorms_host(c, T1, L, tr2))) return r;
+        double tmax = 0.0;
+        for (int i = 0; i < L; ++i) {
+            true_rel[i] = std::sqrt(tr2[i]) / bnorm[i];
+            tmax = std::fmax(tmax, std::isfinite(true_rel[i]) ? true_rel[i] : INFINITY);
+        }
+        if (status == WD_OK && tmax > tol) {
+            if (restarts < max_restarts) {
+                ++restarts;
+                use_x0 = true;
+                continue;
+            }
+            status = WD_NOT_CONVERGED;
+        }
+        break;
+    }
+    WD_TRY_HIP(hipStreamSynchronize(st));
+    const double secs = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+    if (info) {
+        std::memset(info, 0, sizeof(*info));
+        info->status = status < 0 ? WD_NOT_CONVERGED : status;
+        info->iterations = iters;
+        info->total_iterations = total_iters;
+        info->restarts = restarts;
+        info->mvm_paper = S.mvm_paper;
+        info->mvm_actual = S.mvm_actual;
+        info->seconds = secs;
+        info->bytes_alg = S.bytes;
+        for (int i = 0; i < L; ++i) {
+            info->true_residual[i] = true_rel[i];
+            info->recursive_residual[i] = rec_rel[i];
+        }
+    }
+    return status;
+}
+
+}  // extern "C"

@@ -1,0 +1,469 @@
+// Multi-right-hand-side Wilson-clover hopping kernels: the operator
+// Y = A X and the sweeps of the Jacobi preconditioner (Sec. 2).
+//
+// One thread owns one lattice site and a tile of CT columns; the tiles of
+// a site block sit in the same workgroup (threadIdx.y), so each gauge link
+// fetched from HBM is reused from cache by all column tiles and from
+// registers by the CT columns of a thread.  Spinor and link arrays are
+// site-fastest (structure of arrays), so each load instruction of a
+// wavefront reads 64 consecutive sites.
+//
+// The hop uses the rank-2 spin projectors of the chiral basis: for the
+// forward hop (1 - g_mu) psi = (h, -B^dag h) with h = u - B d, for the
+// backward hop (1 + g_mu) psi = (h, B^dag h) with h = u + B d, where u and d
+// are the upper and lower spin pairs and g_mu = [[0, B], [B^dag, 0]] with
+// B = -i s_k (k = x, y, z) and B = 1 (t).  Only the two-spinor h is
+// multiplied by the link.
+//
+// Modes:
+//   APPLY  Y = T X - kappa H X                     (the operator A)
+//   JBLOCK Y = T^{-1} (Rh + kappa H X)             (Jacobi sweep, A_D = T)
+//   JPOINT Y = D^{-1} (Rh + kappa H X - (T - D) X) (Jacobi sweep, A_D = diag T)
+// The links arrive pre-multiplied by kappa.
+#include <cstdlib>
+
+#include "wd_internal.h"
+
+namespace wd {
+
+namespace {
+
+enum { APPLY = 0, JBLOCK = 1, JPOINT = 2 };
+
+// Load the 18 pairs of one chiral 6x6 Hermitian block (packed) and expand to
+// a full matrix held as 6 real diagonal entries and 15 complex upper entries.
+// C is the field base; plane k of it starts at C + k*V; boff is the site's
+// byte offset inside a plane.
+template <class S>
+struct Herm6 {
+    typename S::R d[6];
+    cx<typename S::R> o[15];
+    __device__ __forceinline__ void load(const typename S::P* __restrict__ C, int chir, uint32_t boff, size_t V) {
+#pragma unroll
+        for (int i = 0; i < 3; ++i) {
+            const cx<typename S::R> p = S::ldb(C + (size_t)(chir * 18 + i) * V, boff);
+            d[2 * i] = p.re;
+            d[2 * i + 1] = p.im;
+        }
+#pragma unroll
+        for (int p = 0; p < 15; ++p) o[p] = S::ldb(C + (size_t)(chir * 18 + 3 + p) * V, boff);
+    }
+    // element (i, j) as a complex number
+    __device__ __forceinline__ cx<typename S::R> at(int i, int j) const {
+        using R = typename S::R;
+        if (i == j) return cx<R>{d[i], R(0)};
+        if (i < j) return o[herm_index(i, j)];
+        return conj(o[herm_index(j, i)]);
+    }
+};
+
+// acc (+/-)= projected-and-multiplied hop contribution of direction MU.
+// FWD: link U applied to (u - B d); BWD: U^dag applied to (u + B d).
+template <typename R, int MU, bool FWD, bool ADD>
+__device__ __forceinline__ void hop_dir(cx<R> (&acc)[12], const cx<R> (&u)[9], const cx<R> (&p)[12]) {
+    // p is the neighbour spinor, index 3*spin + colour
+    cx<R> h0[3], h1[3];
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+        const cx<R> s0 = p[c], s1 = p[3 + c], s2 = p[6 + c], s3 = p[9 + c];
+        if (MU == 0) {
+            h0[c] = FWD ? s0 + ti(s3) : s0 - ti(s3);
+            h1[c] = FWD ? s1 + ti(s2) : s1 - ti(s2);
+        } else if (MU == 1) {
+            h0[c] = FWD ? s0 + s3 : s0 - s3;
+            h1[c] = FWD ? s1 - s2 : s1 + s2;
+        } else if (MU == 2) {
+            h0[c] = FWD ? s0 + ti(s2) : s0 - ti(s2);
+            h1[c] = FWD ? s1 - ti(s3) : s1 + ti(s3);
+        } else {
+            h0[c] = FWD ? s0 - s2 : s0 + s2;
+            h1[c] = FWD ? s1 - s3 : s1 + s3;
+        }
+    }
+    // colour: g = U h (forward) or U^dag h (backward)
+    cx<R> g0[3], g1[3];
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        cx<R> r0 = {R(0), R(0)}, r1 = {R(0), R(0)};
+#pragma unroll
+        for (int b = 0; b < 3; ++b) {
+            if (FWD) {
+                cfma(r0, u[a * 3 + b], h0[b]);
+                cfma(r1, u[a * 3 + b], h1[b]);
+            } else {
+                cfmac(r0, u[b * 3 + a], h0[b]);
+                cfmac(r1, u[b * 3 + a], h1[b]);
+            }
+        }
+        g0[a] = r0;
+        g1[a] = r1;
+    }
+    // reconstruct the lower spin pair and accumulate
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        cx<R> l2, l3;
+        if (MU == 0) {
+            l2 = FWD ? tmi(g1[a]) : ti(g1[a]);
+            l3 = FWD ? tmi(g0[a]) : ti(g0[a]);
+        } else if (MU == 1) {
+            l2 = FWD ? -g1[a] : g1[a];
+            l3 = FWD ? g0[a] : -g0[a];
+        } else if (MU == 2) {
+            l2 = FWD ? tmi(g0[a]) : ti(g0[a]);
+            l3 = FWD ? ti(g1[a]) : tmi(g1[a]);
+        } else {
+            l2 = FWD ? -g0[a] : g0[a];
+            l3 = FWD ? -g1[a] : g1[a];
+        }
+        if (ADD) {
+            acc[a] = acc[a] + g0[a];
+            acc[3 + a] = acc[3 + a] + g1[a];
+            acc[6 + a] = acc[6 + a] + l2;
+            acc[9 + a] = acc[9 + a] + l3;
+        } else {
+            acc[a] = acc[a] - g0[a];
+            acc[3 + a] = acc[3 + a] - g1[a];
+            acc[6 + a] = acc[6 + a] - l2;
+            acc[9 + a] = acc[9 + a] - l3;
+        }
+    }
+}
+
+// One hop direction for the CT columns of this thread: the link is loaded
+// once and applied to every column.  Xc is the wave-uniform base of the
+// thread's first column; link_off and nb_off are byte offsets of the link's
+// site and of the neighbour site inside one plane.
+template <class S, int MU, bool FWD, bool ADD, int CT>
+__device__ __forceinline__ void hop_all(cx<typename S::R> (&acc)[CT][12], const typename S::P* __restrict__ Uk,
+                                        const typename S::P* __restrict__ Xc, uint32_t link_off, uint32_t nb_off,
+                                        size_t V) {
+    using R = typename S::R;
+    // keep each direction's loads and arithmetic together: without this fence
+    // the scheduler hoists the loads of all eight directions and spills
+    __builtin_amdgcn_sched_barrier(0);
+    cx<R> u[9];
+#pragma unroll
+    for (int k = 0; k < 9; ++k) u[k] = S::ldb(Uk + (size_t)(MU * 9 + k) * V, link_off);
+#pragma unroll
+    for (int c = 0; c < CT; ++c) {
+        cx<R> p[12];
+        const typename S::P* xc = Xc + (size_t)c * 12 * V;
+#pragma unroll
+        for (int k = 0; k < 12; ++k) p[k] = S::ldb(xc + (size_t)k * V, nb_off);
+        hop_dir<R, MU, FWD, ADD>(acc[c], u, p);
+    }
+}
+
+template <class SY, typename R>
+__device__ __forceinline__ void store_out(typename SY::P* base, uint32_t boff, cx<R> v) {
+    SY::stb(base, boff, cx<typename SY::R>{(typename SY::R)v.re, (typename SY::R)v.im});
+}
+
+// SF: storage of links, clover and the X / Rh inputs (and compute type);
+// SY: storage of the output.
+template <class SF, class SY, int CT, int MODE>
+__global__ void __launch_bounds__(256)
+    k_hop(const Geom g, const typename SF::P* __restrict__ Uk, const typename SF::P* __restrict__ Cl,
+          const typename SF::P* __restrict__ X, const typename SF::P* __restrict__ Rh, typename SY::P* __restrict__ Y,
+          const int col_begin, const int ntiles, const int tiles_per_group, const int groups) {
+    using R = typename SF::R;
+    using PF = typename SF::P;
+    using PY = typename SY::P;
+    const int lin = xcd_remap(blockIdx.x, gridDim.x);
+    const int site_blk = lin / groups;
+    // blockDim.x == 64: threadIdx.y is the same for the whole wavefront
+    const int ty = __builtin_amdgcn_readfirstlane(threadIdx.y);
+    const int tile = (lin % groups) * tiles_per_group + ty;
+    if (tile >= ntiles) return;
+    const int c0 = col_begin + tile * CT;
+    const int s = site_blk * 64 + threadIdx.x;
+    if (s >= g.V) return;
+    const size_t V = g.V;
+    const size_t cs = 12 * V;  // column stride
+
+    const int x = s % g.lx;
+    const int y = (s / g.lx) % g.ly;
+    const int z = (s / g.sxy) % g.lz;
+    const int t = s / g.sxyz;
+    const uint32_t PB = sizeof(PF);
+    const uint32_t o_s = (uint32_t)s * PB;
+    const uint32_t o_fx = (uint32_t)((x == g.lx - 1) ? s - (g.lx - 1) : s + 1) * PB;
+    const uint32_t o_bx = (uint32_t)((x == 0) ? s + (g.lx - 1) : s - 1) * PB;
+    const uint32_t o_fy = (uint32_t)((y == g.ly - 1) ? s - (g.ly - 1) * g.lx : s + g.lx) * PB;
+    const uint32_t o_by = (uint32_t)((y == 0) ? s + (g.ly - 1) * g.lx : s - g.lx) * PB;
+    const uint32_t o_fz = (uint32_t)((z == g.lz - 1) ? s - (g.lz - 1) * g.sxy : s + g.sxy) * PB;
+    const uint32_t o_bz = (uint32_t)((z == 0) ? s + (g.lz - 1) * g.sxy : s - g.sxy) * PB;
+    const uint32_t o_ft = (uint32_t)((t == g.lt - 1) ? s - (g.lt - 1) * g.sxyz : s + g.sxyz) * PB;
+    const uint32_t o_bt = (uint32_t)((t == 0) ? s + (g.lt - 1) * g.sxyz : s - g.sxyz) * PB;
+    const PF* Xc = X + (size_t)c0 * cs;
+
+    cx<R> acc[CT][12];
+    if (MODE == APPLY) {
+        // acc = T X(s), one chiral block at a time
+#pragma unroll
+        for (int chir = 0; chir < 2; ++chir) {
+            Herm6<SF> T;
+            T.load(Cl, chir, o_s, V);
+#pragma unroll
+            for (int c = 0; c < CT; ++c) {
+                cx<R> v[6];
+#pragma unroll
+                for (int k = 0; k < 6; ++k) v[k] = SF::ldb(Xc + (size_t)c * cs + (size_t)(6 * chir + k) * V, o_s);
+#pragma unroll
+                for (int i = 0; i < 6; ++i) {
+                    cx<R> r = {R(0), R(0)};
+#pragma unroll
+                    for (int j = 0; j < 6; ++j) cfma(r, T.at(i, j), v[j]);
+                    acc[c][6 * chir + i] = r;
+                }
+            }
+        }
+    } else {
+        const PF* Rc = Rh + (size_t)c0 * cs;
+#pragma unroll
+        for (int c = 0; c < CT; ++c) {
+#pragma unroll
+            for (int k = 0; k < 12; ++k)
+                acc[c][k] = SF::ldb(Rc + (size_t)c * cs + (size_t)k * V, o_s);
+        }
+    }
+
+    constexpr bool ADD = (MODE != APPLY);
+    hop_all<SF, 0, true, ADD, CT>(acc, Uk, Xc, o_s, o_fx, V);
+    hop_all<SF, 0, false, ADD, CT>(acc, Uk, Xc, o_bx, o_bx, V);
+    hop_all<SF, 1, true, ADD, CT>(acc, Uk, Xc, o_s, o_fy, V);
+    hop_all<SF, 1, false, ADD, CT>(acc, Uk, Xc, o_by, o_by, V);
+    hop_all<SF, 2, true, ADD, CT>(acc, Uk, Xc, o_s, o_fz, V);
+    hop_all<SF, 2, false, ADD, CT>(acc, Uk, Xc, o_bz, o_bz, V);
+    hop_all<SF, 3, true, ADD, CT>(acc, Uk, Xc, o_s, o_ft, V);
+    hop_all<SF, 3, false, ADD, CT>(acc, Uk, Xc, o_bt, o_bt, V);
+    __builtin_amdgcn_sched_barrier(0);
+
+    PY* Yc = Y + (size_t)c0 * cs;
+    if (MODE == APPLY) {
+#pragma unroll
+        for (int c = 0; c < CT; ++c)
+#pragma unroll
+            for (int k = 0; k < 12; ++k) store_out<SY>(Yc + (size_t)c * cs + (size_t)k * V, o_s, acc[c][k]);
+    } else {
+#pragma unroll
+        for (int chir = 0; chir < 2; ++chir) {
+            Herm6<SF> T;
+            T.load(Cl, chir, o_s, V);
+#pragma unroll
+            for (int c = 0; c < CT; ++c) {
+                {
+                    cx<R> xs[6];
+                    if (MODE == JPOINT) {
+#pragma unroll
+                        for (int k = 0; k < 6; ++k)
+                            xs[k] = SF::ldb(Xc + (size_t)c * cs + (size_t)(6 * chir + k) * V, o_s);
+                    }
+#pragma unroll
+                    for (int i = 0; i < 6; ++i) {
+                        cx<R> r;
+                        if (MODE == JBLOCK) {
+                            r = {R(0), R(0)};
+#pragma unroll
+                            for (int j = 0; j < 6; ++j) cfma(r, T.at(i, j), acc[c][6 * chir + j]);
+                        } else {
+                            // point reading: the diagonal slots hold 1/d
+                            cx<R> q = acc[c][6 * chir + i];
+#pragma unroll
+                            for (int j = 0; j < 6; ++j)
+                                if (j != i) q = q - T.at(i, j) * xs[j];
+                            r = T.d[i] * q;
+                        }
+                        store_out<SY>(Yc + (size_t)c * cs + (size_t)(6 * chir + i) * V, o_s, r);
+                    }
+                }
+            }
+        }
+    }
+}
+
+// First Jacobi sweep from G_0 = 0: Y = A_D^{-1} R (site-local, no hop).
+// SI: input storage, SF: clover storage and compute, SY: output storage;
+// with RL != nullptr the input is also written out in format SF (the
+// low-precision copy of the right-hand side used by later sweeps).
+template <class SI, class SF, class SY, int MODE>
+__global__ void __launch_bounds__(256)
+    k_first_sweep(const Geom g, const typename SF::P* __restrict__ Cl, const typename SI::P* __restrict__ Rin,
+                  typename SF::P* __restrict__ RL, typename SY::P* __restrict__ Y, const int L) {
+    using R = typename SF::R;
+    const size_t V = g.V;
+    const int sblocks = (g.V + 255) / 256;
+    const int col = blockIdx.x / sblocks;
+    const int s = (blockIdx.x % sblocks) * 256 + threadIdx.x;
+    if (s >= g.V || col >= L) return;
+    const size_t cs = 12 * V;
+    const uint32_t oF = (uint32_t)s * sizeof(typename SF::P);
+    const uint32_t oI = (uint32_t)s * sizeof(typename SI::P);
+    const uint32_t oY = (uint32_t)s * sizeof(typename SY::P);
+    const typename SI::P* Rc = Rin + (size_t)col * cs;
+#pragma unroll
+    for (int chir = 0; chir < 2; ++chir) {
+        Herm6<SF> T;
+        T.load(Cl, chir, oF, V);
+        cx<R> v[6];
+#pragma unroll
+        for (int k = 0; k < 6; ++k) {
+            const auto w = SI::ldb(Rc + (size_t)(6 * chir + k) * V, oI);
+            v[k] = {(R)w.re, (R)w.im};
+            if (RL != nullptr) {
+                // later sweeps read the rounded copy; use the same rounded value here
+                SF::stb(RL + (size_t)col * cs + (size_t)(6 * chir + k) * V, oF, v[k]);
+                v[k] = SF::rnd(v[k]);
+            }
+        }
+#pragma unroll
+        for (int r = 0; r < 6; ++r) {
+            cx<R> o = {R(0), R(0)};
+            if (MODE == JBLOCK) {
+#pragma unroll
+                for (int j = 0; j < 6; ++j) cfma(o, T.at(r, j), v[j]);
+            } else {
+                o = T.d[r] * v[r];
+            }
+            store_out<SY>(Y + (size_t)col * cs + (size_t)(6 * chir + r) * V, oY, o);
+        }
+    }
+}
+
+template <class S>
+__global__ void k_from_lowp(const typename S::P* __restrict__ src, double2* __restrict__ dst, size_t n) {
+    const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const auto v = S::ld(src, i);
+    dst[i] = make_double2((double)v.re, (double)v.im);
+}
+
+// Columns per thread for L right-hand sides (overridable for tuning).
+int tile_cols(int L) {
+    static int forced = [] {
+        const char* e = std::getenv("WDSOLVE_HOP_CT");
+        return e ? std::atoi(e) : 0;
+    }();
+    if (forced >= 1 && forced <= 4) return forced < L ? forced : L;
+    if (L <= 4) return 1;
+    if (L <= 8) return 2;
+    if (L <= 12) return 3;
+    return 4;
+}
+
+template <class SF, class SY, int MODE, int CT>
+hipError_t launch_hop_ct(const Geom& g, const void* Uk, const void* Cl, const void* X, const void* Rh, void* Y,
+                         int col_begin, int ntiles, hipStream_t s) {
+    // up to 4 column tiles share one workgroup (and so the links in cache)
+    const int groups = (ntiles + 3) / 4;
+    const int tpg = (ntiles + groups - 1) / groups;
+    const int sblk = (g.V + 63) / 64;
+    dim3 block(64, tpg), grid(sblk * groups);
+    using PF = typename SF::P;
+    using PY = typename SY::P;
+    k_hop<SF, SY, CT, MODE><<<grid, block, 0, s>>>(g, (const PF*)Uk, (const PF*)Cl, (const PF*)X, (const PF*)Rh,
+                                                   (PY*)Y, col_begin, ntiles, tpg, groups);
+    return hipGetLastError();
+}
+
+template <class SF, class SY, int MODE>
+hipError_t launch_hop_cols(const Geom& g, const void* Uk, const void* Cl, const void* X, const void* Rh, void* Y,
+                           int CT, int col_begin, int ntiles, hipStream_t s) {
+    switch (CT) {
+        case 1: return launch_hop_ct<SF, SY, MODE, 1>(g, Uk, Cl, X, Rh, Y, col_begin, ntiles, s);
+        case 2: return launch_hop_ct<SF, SY, MODE, 2>(g, Uk, Cl, X, Rh, Y, col_begin, ntiles, s);
+        case 3: return launch_hop_ct<SF, SY, MODE, 3>(g, Uk, Cl, X, Rh, Y, col_begin, ntiles, s);
+        case 4: return launch_hop_ct<SF, SY, MODE, 4>(g, Uk, Cl, X, Rh, Y, col_begin, ntiles, s);
+        default: return hipErrorInvalidValue;
+    }
+}
+
+// L columns: full tiles of CT columns, then one launch for the remainder.
+template <class SF, class SY, int MODE>
+hipError_t launch_hop_t(const Geom& g, const void* Uk, const void* Cl, const void* X, const void* Rh, void* Y, int L,
+                        hipStream_t s) {
+    const int CT = tile_cols(L);
+    const int full = L / CT, rem = L % CT;
+    hipError_t e = launch_hop_cols<SF, SY, MODE>(g, Uk, Cl, X, Rh, Y, CT, 0, full, s);
+    if (e != hipSuccess || rem == 0) return e;
+    return launch_hop_cols<SF, SY, MODE>(g, Uk, Cl, X, Rh, Y, rem, full * CT, 1, s);
+}
+
+template <class SI, class SF, class SY>
+hipError_t launch_first(const wd_ctx* c, const void* Cl, const void* Rin, void* RL, void* Y, int L, hipStream_t s) {
+    const unsigned nb = (unsigned)((c->g.V + 255) / 256) * L;
+    if (c->jacobi_kind == WD_JACOBI_POINT)
+        k_first_sweep<SI, SF, SY, JPOINT><<<nb, 256, 0, s>>>(c->g, (const typename SF::P*)Cl,
+                                                              (const typename SI::P*)Rin, (typename SF::P*)RL,
+                                                              (typename SY::P*)Y, L);
+    else
+        k_first_sweep<SI, SF, SY, JBLOCK><<<nb, 256, 0, s>>>(c->g, (const typename SF::P*)Cl,
+                                                              (const typename SI::P*)Rin, (typename SF::P*)RL,
+                                                              (typename SY::P*)Y, L);
+    return hipGetLastError();
+}
+
+template <class SF, class SY>
+hipError_t launch_sweep(const wd_ctx* c, int pi, const void* X, const void* Rh, void* Y, int L, hipStream_t s) {
+    if (c->jacobi_kind == WD_JACOBI_POINT)
+        return launch_hop_t<SF, SY, JPOINT>(c->g, c->f.Uk[pi], c->f.Tp[pi], X, Rh, Y, L, s);
+    return launch_hop_t<SF, SY, JBLOCK>(c->g, c->f.Uk[pi], c->f.Ti[pi], X, Rh, Y, L, s);
+}
+
+// j sweeps in storage format S (FP32 or BF16), FP64 in and out.
+template <class S>
+hipError_t jacobi_lowp(wd_ctx* c, int pi, const double2* R, double2* Z, int L, int j, hipStream_t s) {
+    const void* clf = (c->jacobi_kind == WD_JACOBI_POINT) ? c->f.Tp[pi] : c->f.Ti[pi];
+    void* rl = c->lp[2];
+    if (j == 1) return launch_first<StF64, S, StF64>(c, clf, R, nullptr, Z, L, s);
+    hipError_t e = launch_first<StF64, S, S>(c, clf, R, rl, c->lp[0], L, s);
+    if (e != hipSuccess) return e;
+    int cur = 0;
+    for (int i = 2; i < j; ++i) {
+        e = launch_sweep<S, S>(c, pi, c->lp[cur], rl, c->lp[1 - cur], L, s);
+        if (e != hipSuccess) return e;
+        cur = 1 - cur;
+    }
+    return launch_sweep<S, StF64>(c, pi, c->lp[cur], rl, Z, L, s);
+}
+
+}  // namespace
+
+hipError_t launch_apply_A(const wd_ctx* c, const double2* X, double2* Y, int L, hipStream_t s) {
+    return launch_hop_t<StF64, StF64, APPLY>(c->g, c->f.Uk[0], c->f.T, X, nullptr, Y, L, s);
+}
+
+hipError_t launch_sweep_f64(const wd_ctx* c, const double2* X, const double2* R, double2* Y, int L, hipStream_t s) {
+    return launch_sweep<StF64, StF64>(c, 0, X, R, Y, L, s);
+}
+
+hipError_t launch_apply_A_lowp(wd_ctx* c, const double2* X, double2* Y, int L, Prec p, hipStream_t s) {
+    const size_t n = (size_t)12 * c->g.V * L;
+    hipError_t e = launch_to_lowp(X, c->lp[0], p, n, s);
+    if (e != hipSuccess) return e;
+    if (p == Prec::F32)
+        return launch_hop_t<StF32, StF64, APPLY>(c->g, c->f.Uk[1], c->f.Tc[1], c->lp[0], nullptr, Y, L, s);
+    return launch_hop_t<StBF16, StF64, APPLY>(c->g, c->f.Uk[2], c->f.Tc[2], c->lp[0], nullptr, Y, L, s);
+}
+
+hipError_t launch_jacobi(wd_ctx* c, const double2* R, double2* Z, int L, int j, Prec p, hipStream_t s) {
+    const size_t n = (size_t)12 * c->g.V * L;
+    if (j == 0) return launch_copy(Z, R, n, s);
+    if (p == Prec::F32) return jacobi_lowp<StF32>(c, 1, R, Z, L, j, s);
+    if (p == Prec::BF16) return jacobi_lowp<StBF16>(c, 2, R, Z, L, j, s);
+    const void* clf = (c->jacobi_kind == WD_JACOBI_POINT) ? c->f.Tp[0] : c->f.Ti[0];
+    // FP64: alternate between Z and the scratch block so that sweep j lands in Z
+    double2* tmp = c->ws[10];
+    double2* out = ((j - 1) % 2 == 0) ? Z : tmp;
+    hipError_t e = launch_first<StF64, StF64, StF64>(c, clf, R, nullptr, out, L, s);
+    if (e != hipSuccess) return e;
+    for (int i = 2; i <= j; ++i) {
+        double2* in = out;
+        out = ((j - i) % 2 == 0) ? Z : tmp;
+        e = launch_sweep<StF64, StF64>(c, 0, in, R, out, L, s);
+        if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
+}
+
+}  // namespace wd

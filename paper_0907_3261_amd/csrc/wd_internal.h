@@ -1,0 +1,265 @@
+// Internal declarations of the wdsolve library: device data layouts,
+// complex arithmetic, storage formats and the kernel launchers shared by the
+// translation units.  Nothing here is part of the public ABI.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <cstddef>
+#include <cstdint>
+
+#include "../../include/wdsolve.h"
+
+namespace wd {
+
+// ---------------------------------------------------------------------------
+// Complex numbers over a compute real R (double or float)
+// ---------------------------------------------------------------------------
+template <typename R>
+struct cx {
+    R re, im;
+};
+
+template <typename R>
+__host__ __device__ __forceinline__ cx<R> mk(R a, R b) { return cx<R>{a, b}; }
+template <typename R>
+__host__ __device__ __forceinline__ cx<R> operator+(cx<R> a, cx<R> b) { return {a.re + b.re, a.im + b.im}; }
+template <typename R>
+__host__ __device__ __forceinline__ cx<R> operator-(cx<R> a, cx<R> b) { return {a.re - b.re, a.im - b.im}; }
+template <typename R>
+__host__ __device__ __forceinline__ cx<R> operator-(cx<R> a) { return {-a.re, -a.im}; }
+template <typename R>
+__host__ __device__ __forceinline__ cx<R> operator*(cx<R> a, cx<R> b) {
+    return {a.re * b.re - a.im * b.im, a.re * b.im + a.im * b.re};
+}
+template <typename R>
+__host__ __device__ __forceinline__ cx<R> operator*(R s, cx<R> a) { return {s * a.re, s * a.im}; }
+// conj(a) * b
+template <typename R>
+__host__ __device__ __forceinline__ cx<R> cmulc(cx<R> a, cx<R> b) {
+    return {a.re * b.re + a.im * b.im, a.re * b.im - a.im * b.re};
+}
+template <typename R>
+__host__ __device__ __forceinline__ cx<R> conj(cx<R> a) { return {a.re, -a.im}; }
+// i * a and -i * a
+template <typename R>
+__host__ __device__ __forceinline__ cx<R> ti(cx<R> a) { return {-a.im, a.re}; }
+template <typename R>
+__host__ __device__ __forceinline__ cx<R> tmi(cx<R> a) { return {a.im, -a.re}; }
+// a += b * c, a += conj(b) * c
+template <typename R>
+__host__ __device__ __forceinline__ void cfma(cx<R>& a, cx<R> b, cx<R> c) {
+    a.re = fma(b.re, c.re, fma(-b.im, c.im, a.re));
+    a.im = fma(b.re, c.im, fma(b.im, c.re, a.im));
+}
+template <typename R>
+__host__ __device__ __forceinline__ void cfmac(cx<R>& a, cx<R> b, cx<R> c) {
+    a.re = fma(b.re, c.re, fma(b.im, c.im, a.re));
+    a.im = fma(b.re, c.im, fma(-b.im, c.re, a.im));
+}
+
+// ---------------------------------------------------------------------------
+// Storage formats of complex pairs in device memory
+// ---------------------------------------------------------------------------
+// Every field lives as an array of complex "pairs" (re, im) in one of three
+// storage formats; kernels load into and compute in the format's real R.
+//
+// ldb/stb address a pair by a wave-uniform plane base pointer plus a 32-bit
+// per-lane byte offset, which maps to the scalar-base + vector-offset form
+// of the global memory instructions (one offset register serves every plane
+// of a field instead of one 64-bit address per load).
+#define WD_BYTE_OFFSET_ACCESSORS                                                        \
+    __device__ __forceinline__ static cx<R> ldb(const P* base, uint32_t boff) {         \
+        return ld(reinterpret_cast<const P*>(reinterpret_cast<const char*>(base) + boff), 0); \
+    }                                                                                   \
+    __device__ __forceinline__ static void stb(P* base, uint32_t boff, cx<R> v) {       \
+        st(reinterpret_cast<P*>(reinterpret_cast<char*>(base) + boff), 0, v);          \
+    }
+struct StF64 {
+    using R = double;
+    using P = double2;
+    static constexpr int bytes = 16;
+    __device__ __forceinline__ static cx<R> ld(const P* p, size_t i) {
+        P v = p[i];
+        return {v.x, v.y};
+    }
+    __device__ __forceinline__ static void st(P* p, size_t i, cx<R> v) { p[i] = make_double2(v.re, v.im); }
+    __device__ __forceinline__ static cx<R> rnd(cx<R> v) { return v; }
+    WD_BYTE_OFFSET_ACCESSORS
+};
+
+struct StF32 {
+    using R = float;
+    using P = float2;
+    static constexpr int bytes = 8;
+    __device__ __forceinline__ static cx<R> ld(const P* p, size_t i) {
+        P v = p[i];
+        return {v.x, v.y};
+    }
+    __device__ __forceinline__ static void st(P* p, size_t i, cx<R> v) { p[i] = make_float2(v.re, v.im); }
+    __device__ __forceinline__ static cx<R> rnd(cx<R> v) { return v; }
+    WD_BYTE_OFFSET_ACCESSORS
+};
+
+// bfloat16 pair packed in 32 bits: low half = re, high half = im.
+__host__ __device__ __forceinline__ uint32_t f32_to_bf16_rne(float f) {
+    uint32_t u = __float_as_uint(f);
+    if ((u & 0x7f800000u) == 0x7f800000u && (u & 0x007fffffu)) return (u >> 16) | 0x40u;  // quiet NaN
+    u += 0x7fffu + ((u >> 16) & 1u);
+    return u >> 16;
+}
+struct StBF16 {
+    using R = float;
+    using P = uint32_t;
+    static constexpr int bytes = 4;
+    __device__ __forceinline__ static cx<R> ld(const P* p, size_t i) {
+        uint32_t v = p[i];
+        return {__uint_as_float(v << 16), __uint_as_float(v & 0xffff0000u)};
+    }
+    __device__ __forceinline__ static void st(P* p, size_t i, cx<R> v) {
+        p[i] = f32_to_bf16_rne(v.re) | (f32_to_bf16_rne(v.im) << 16);
+    }
+    // value after a round trip through the storage format
+    __device__ __forceinline__ static cx<R> rnd(cx<R> v) {
+        return {__uint_as_float(f32_to_bf16_rne(v.re) << 16), __uint_as_float(f32_to_bf16_rne(v.im) << 16)};
+    }
+    WD_BYTE_OFFSET_ACCESSORS
+};
+
+// ---------------------------------------------------------------------------
+// Lattice geometry
+// ---------------------------------------------------------------------------
+struct Geom {
+    int lx, ly, lz, lt;
+    int V;          // number of sites
+    int sxy;        // lx*ly
+    int sxyz;       // lx*ly*lz
+};
+
+// Device data layouts (all "pair" arrays, site index fastest):
+//   links      [mu][a*3+b][V]               4*9 pairs per site
+//   clover     [chirality c][18][V]         per 6x6 Hermitian block: entries
+//              0..2 hold the six real diagonal elements as (d0,d1),(d2,d3),(d4,d5),
+//              entries 3..17 the upper off-diagonal elements (i<j) in row order
+//   block vec  [column][k = 3*spin+colour][V]
+__host__ __device__ constexpr int herm_index(int i, int j) {  // i < j, 6x6
+    return i * 6 - i * (i + 1) / 2 + (j - i - 1);
+}
+
+// Workgroup index -> tile index such that each of the 8 XCDs (which receive
+// workgroups round-robin) works on one contiguous range of tiles.
+__device__ __forceinline__ int xcd_remap(int b, int nb) {
+    const int nx = 8;
+    const int q = nb / nx, r = nb % nx;
+    const int x = b % nx, i = b / nx;
+    return x * q + (x < r ? x : r) + i;
+}
+
+// ---------------------------------------------------------------------------
+// Context
+// ---------------------------------------------------------------------------
+struct Fields {
+    double2* U = nullptr;      // FP64 links, antiperiodic sign folded in (clover, learned layers)
+    double2* T = nullptr;      // FP64 clover T (operator A)
+    // per precision (index Prec): kappa-scaled links, T^{-1} (block reading),
+    // point form (1/diag(T) on the diagonal slots, T's off-diagonals), T
+    void* Uk[3] = {};
+    void* Ti[3] = {};
+    void* Tp[3] = {};
+    void* Tc[3] = {};
+};
+
+enum class Prec { F64 = 0, F32 = 1, BF16 = 2 };
+
+}  // namespace wd
+
+struct wd_ctx {
+    wd::Geom g;
+    int bc_t = 0;
+    int max_L = 0;
+    hipStream_t stream = nullptr;
+    bool have_links = false;
+    bool have_params = false;
+    double kappa = 0, csw = 0;
+    int jacobi_kind = WD_JACOBI_BLOCK;
+    wd::Fields f;
+    // solver workspace: N x max_L FP64 blocks
+    double2* ws[12] = {};
+    // low-precision Jacobi iterates: two ping-pong blocks and the right-hand side copy
+    void* lp[3] = {};
+    // reduction partials and small control data
+    double2* partial = nullptr;
+    int n_partial_blocks = 0;
+    double2* small = nullptr;     // L x L matrices, scalars (see wd_blas.hip)
+    int* dstatus = nullptr;
+    double* host_ctl = nullptr;   // pinned host mirror of per-iteration control data
+    // learned preconditioner
+    float2* theta = nullptr;
+    bool have_theta = false;
+};
+
+namespace wd {
+
+// ---- setup (wd_setup.hip)
+hipError_t launch_links_from_abi(const double2* Uabi, double2* U, const Geom& g, int bc_t, hipStream_t s);
+hipError_t launch_clover(const double2* U, double2* T, double2* Ti, const Geom& g, double kappa, double csw,
+                         hipStream_t s);
+// dst = scale * src, stored in precision p (n complex pairs)
+hipError_t launch_convert(const double2* src, void* dst, Prec p, double scale, size_t n, hipStream_t s);
+// point form of T: diagonal slots replaced by 1/diag, off-diagonal slots kept
+hipError_t launch_point_form(const double2* T, double2* Tp, size_t V, hipStream_t s);
+// convert an FP64 block vector to precision p and back
+hipError_t launch_to_lowp(const double2* src, void* dst, Prec p, size_t n, hipStream_t s);
+
+// ---- Wilson hopping kernels (wd_dslash.hip)
+// Y = A X (FP64)
+hipError_t launch_apply_A(const wd_ctx* c, const double2* X, double2* Y, int L, hipStream_t s);
+// Z = M R with j sweeps in precision p; tmp is a scratch block of L columns
+hipError_t launch_jacobi(wd_ctx* c, const double2* R, double2* Z, int L, int j, Prec p, hipStream_t s);
+// one Jacobi sweep Y = A_D^{-1}(R + kappa H X) in FP64
+hipError_t launch_sweep_f64(const wd_ctx* c, const double2* X, const double2* R, double2* Y, int L, hipStream_t s);
+// algorithmic HBM bytes per site of the kernels (FP64 storage, L columns)
+inline double bytes_apply(int L) { return 1152.0 + 384.0 * L; }
+inline double bytes_sweep(int L) { return 1152.0 + 576.0 * L; }
+inline double bytes_first_sweep(int L) { return 576.0 + 384.0 * L; }
+// low precision application of A (diagnostic): Y (FP64) = A X computed in p
+hipError_t launch_apply_A_lowp(wd_ctx* c, const double2* X, double2* Y, int L, Prec p, hipStream_t s);
+
+// ---- block kernels (wd_blas.hip)
+size_t partial_stride();  // complex entries per partial block
+int gram_blocks(size_t N);
+// partials of P^H Q over rows (nb blocks)
+hipError_t launch_gram_partials(const double2* P, const double2* Q, size_t N, int L, double2* partial, int nb,
+                                hipStream_t s);
+// reduce partials -> C (L x L row-major) on the device
+hipError_t launch_reduce_gram(const double2* partial, int nb, int L, double2* C, hipStream_t s);
+hipError_t launch_small_solve(const double2* M, const double2* RHS, int L, double2* Z, int* status, hipStream_t s);
+
+// solver-specific fused kernels
+struct SolverBufs {
+    double2* C_r;      // Rt^H R_k           (L x L)
+    double2* C_rn;     // Rt^H R_{k+1}       (L x L)
+    double2* alpha;    // L x L
+    double2* gamma;    // L x L
+    double2* zeta;     // [0] = zeta, [1] = Tr W^H R, [2] = Tr W^H W
+    double* norms;     // L squared column norms of R_{k+1}
+    int* status;       // breakdown / nan flags
+};
+hipError_t launch_gram1(const double2* Rt, const double2* V, const double2* W, const double2* R, size_t N, int L,
+                        double2* partial, int nb, hipStream_t s);
+hipError_t launch_solve_alpha(const double2* partial, int nb, int L, const SolverBufs& b, hipStream_t s);
+hipError_t launch_update_U(const double2* P, const double2* V, const double2* zeta, const double2* alpha,
+                           double2* U, size_t N, int L, hipStream_t s);
+hipError_t launch_update_XR(double2* X, double2* R, const double2* F, const double2* G, const double2* W,
+                            const double2* Y, const double2* Rt, const double2* zeta, size_t N, int L,
+                            double2* partial, int nb, hipStream_t s);
+hipError_t launch_solve_gamma(const double2* partial, int nb, int L, const SolverBufs& b, hipStream_t s);
+hipError_t launch_update_PV(double2* P, double2* V, const double2* R, const double2* W, const double2* U,
+                            const double2* Y, const double2* gamma, size_t N, int L, hipStream_t s);
+// residual helpers
+hipError_t launch_axpby_block(const double2* B, const double2* AX, double2* R, size_t n, hipStream_t s);  // R = B - AX
+hipError_t launch_colnorms(const double2* R, size_t N, int L, double2* partial, int nb, double* norms,
+                           hipStream_t s);
+hipError_t launch_copy(double2* dst, const double2* src, size_t n, hipStream_t s);
+hipError_t launch_zero(double2* dst, size_t n, hipStream_t s);
+
+}  // namespace wd

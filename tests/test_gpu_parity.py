@@ -1,0 +1,368 @@
+"""GPU parity of the HIP path against the FP64 oracle, through the C ABI.
+
+Tolerances: FP64 operator and preconditioner applications agree with the
+oracle to 1e-13 relative (each output element is a short fixed sum, so the
+only difference is rounding order, ~1e-16 per element); solves reach a true
+residual <= 1e-12 per column, checked with the oracle's own operator.
+"""
+
+import sys
+
+import numpy as np
+import pytest
+
+import wdinputs as wi
+from oracle import WilsonClover, gamma5
+from oracle.dirac import SiteOperator
+from oracle.jacobi import jacobi_apply
+from oracle.bbicggr import block_bicggr, true_residual
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+def _say(msg):
+    sys.__stderr__.write(f"[gpu] {msg}\n")
+    sys.__stderr__.flush()
+
+
+@pytest.fixture(autouse=True)
+def _announce(request):
+    _say(request.node.nodeid)
+    yield
+
+
+@pytest.fixture(scope="module")
+def pkg():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_0907_3261_amd as p
+    p.load()
+    return p
+
+
+def _ctx(pkg, dims, U, kappa, csw, bc_t=0, max_L=12, kind=0):
+    c = pkg.Context(dims, bc_t=bc_t, max_L=max_L)
+    c.set_links(U)
+    c.set_params(kappa, csw, kind)
+    return c
+
+
+def _dev(b):
+    return torch.from_numpy(np.ascontiguousarray(b)).to("cuda")
+
+
+def _host(t):
+    torch.cuda.synchronize()
+    return t.cpu().numpy()
+
+
+def _rel(a, b):
+    return np.linalg.norm(a - b) / np.linalg.norm(b)
+
+
+def _maxrel(a, b):
+    return np.max(np.abs(a - b)) / np.max(np.abs(b))
+
+
+CASES = [((4, 4, 4, 4), 0), ((3, 4, 5, 6), 1), ((2, 2, 2, 2), 0), ((8, 6, 4, 10), 1)]
+
+
+# ---------------------------------------------------------------- clover setup
+
+@pytest.mark.parametrize("dims,bc_t", CASES)
+def test_clover_and_inverse(pkg, dims, bc_t):
+    U = wi.random_links(dims, 0.4, 101)
+    op = WilsonClover(dims, U, 0.13, 1.6, bc_t=bc_t)
+    c = _ctx(pkg, dims, U, 0.13, 1.6, bc_t)
+    T = c.clover(0)
+    Ti = c.clover(1)
+    Tor = op.T.reshape(op.V, 12, 12)
+    Tior = op.Tinv.reshape(op.V, 12, 12)
+    for ch in range(2):
+        sl = slice(6 * ch, 6 * ch + 6)
+        assert np.max(np.abs(T[:, ch] - Tor[:, sl, sl])) < 1e-14
+        assert _maxrel(Ti[:, ch], Tior[:, sl, sl]) < 1e-13
+    c.close()
+
+
+# ---------------------------------------------------------------- operator
+
+@pytest.mark.parametrize("dims,bc_t", CASES)
+@pytest.mark.parametrize("L", [1, 4, 5, 12])
+def test_apply_matches_oracle(pkg, dims, bc_t, L):
+    U = wi.random_links(dims, 0.4, 102)
+    op = WilsonClover(dims, U, 0.128, 1.6, bc_t=bc_t)
+    c = _ctx(pkg, dims, U, 0.128, 1.6, bc_t, max_L=12)
+    X = wi.gaussian_block(op.V, L, 103)
+    Y = _host(c.apply(_dev(X)))
+    Yo = op.to_block(op.apply_A(op.from_block(X)))
+    assert _maxrel(Y, Yo) < 1e-13
+    for i in range(L):
+        assert _rel(Y[i], Yo[i]) < 1e-13
+    c.close()
+
+
+def test_apply_max_columns_and_ragged_volume(pkg):
+    dims = (5, 3, 3, 5)           # V = 225: not a multiple of the 64-site tile
+    U = wi.random_links(dims, 0.4, 104)
+    op = WilsonClover(dims, U, 0.12, 1.0)
+    c = _ctx(pkg, dims, U, 0.12, 1.0, max_L=16)
+    X = wi.gaussian_block(op.V, 16, 105)
+    Y = _host(c.apply(_dev(X)))
+    assert _maxrel(Y, op.to_block(op.apply_A(op.from_block(X)))) < 1e-13
+    c.close()
+
+
+def test_apply_gamma5_hermiticity_and_determinism(pkg):
+    dims = (4, 4, 4, 8)
+    U = wi.random_links(dims, 0.3, 106)
+    c = _ctx(pkg, dims, U, 0.135, 1.6, 1)
+    V = wi.volume(dims)
+    phi = wi.gaussian_block(V, 3, 107)
+    psi = wi.gaussian_block(V, 3, 108)
+    g5 = np.diag(gamma5()).real                       # +1, +1, -1, -1
+    g5k = np.repeat(g5, 3)[None, :, None]             # per component k = 3*spin + colour
+    Ag5psi = _host(c.apply(_dev(g5k * psi)))
+    Aphi = _host(c.apply(_dev(phi)))
+    lhs = np.vdot(phi, g5k * Ag5psi)
+    rhs = np.vdot(Aphi, psi)
+    assert abs(lhs - rhs) / abs(lhs) < 1e-13
+    Aphi2 = _host(c.apply(_dev(phi)))
+    assert np.array_equal(Aphi, Aphi2)
+    c.close()
+
+
+def test_apply_rejects_bad_arguments(pkg):
+    dims = (4, 4, 4, 4)
+    c = pkg.Context(dims, max_L=4)
+    X = c.empty_block(2)
+    with pytest.raises(pkg.WDError):          # parameters not set yet
+        c.apply(X)
+    c.set_links(wi.random_links(dims, 0.3, 1))
+    c.set_params(0.12, 1.0)
+    with pytest.raises(pkg.WDError):          # L above max_L
+        c.apply(c.empty_block(5))
+    with pytest.raises(pkg.WDError):          # output aliases input
+        c.apply(X, X)
+    c.close()
+
+
+# ---------------------------------------------------------------- Jacobi
+
+@pytest.mark.parametrize("kind", [0, 1])
+@pytest.mark.parametrize("j", [0, 1, 2, 5, 12])
+def test_jacobi_matches_oracle(pkg, kind, j):
+    dims = (4, 4, 6, 4)
+    U = wi.random_links(dims, 0.3, 109)
+    op = WilsonClover(dims, U, 0.13, 1.6, bc_t=1, jacobi_kind="block" if kind == 0 else "point")
+    c = _ctx(pkg, dims, U, 0.13, 1.6, 1, kind=kind)
+    R = wi.gaussian_block(op.V, 3, 110)
+    Z = _host(c.jacobi(_dev(R), j))
+    Zo = op.to_block(jacobi_apply(op, op.from_block(R), j))
+    assert _maxrel(Z, Zo) < 1e-13
+    c.close()
+
+
+# ---------------------------------------------------------------- block kernels
+
+@pytest.mark.parametrize("L", [1, 3, 12, 16])
+def test_block_gram(pkg, L):
+    dims = (3, 5, 4, 7)
+    c = pkg.Context(dims, max_L=16)
+    V = wi.volume(dims)
+    P = wi.gaussian_block(V, L, 111)
+    Q = wi.gaussian_block(V, L, 112)
+    C = _host(c.gram(_dev(P), _dev(Q)))
+    Pm = P.reshape(L, -1).T
+    Qm = Q.reshape(L, -1).T
+    Co = Pm.conj().T @ Qm
+    assert _maxrel(C, Co) < 1e-13
+    c.close()
+
+
+def test_block_gram_large_rows(pkg):
+    dims = (16, 16, 16, 8)        # N = 393216 rows: many partial blocks
+    c = pkg.Context(dims, max_L=12)
+    V = wi.volume(dims)
+    P = wi.gaussian_block(V, 12, 113)
+    Q = wi.gaussian_block(V, 12, 114)
+    C = _host(c.gram(_dev(P), _dev(Q)))
+    Co = P.reshape(12, -1).conj() @ Q.reshape(12, -1).T
+    assert _maxrel(C, Co) < 1e-13
+    c.close()
+
+
+@pytest.mark.parametrize("L", [1, 2, 7, 12, 16])
+def test_small_solve(pkg, L):
+    c = pkg.Context((2, 2, 2, 2), max_L=16)
+    rng = np.random.default_rng(L)
+    M = rng.standard_normal((L, L)) + 1j * rng.standard_normal((L, L))
+    B = rng.standard_normal((L, L)) + 1j * rng.standard_normal((L, L))
+    Z, ok = c.small_solve(_dev(M), _dev(B))
+    assert ok
+    assert _maxrel(_host(Z), np.linalg.solve(M, B)) < 1e-11
+    if L > 1:
+        Ms = M.copy()
+        Ms[1] = Ms[0]             # exactly singular
+        Z, ok = c.small_solve(_dev(Ms), _dev(B))
+        assert not ok
+    c.close()
+
+
+# ---------------------------------------------------------------- solver
+
+def _workload_ctx(pkg, name):
+    w = wi.workload(name)
+    U = wi.random_links(w["dims"], w["eps"], w["link_seed"])
+    kappa = w["kappa"] if not isinstance(w["kappa"], tuple) else w["kappa"][0]
+    c = _ctx(pkg, w["dims"], U, kappa, w["csw"], w["bc_t"], max_L=12)
+    op = WilsonClover(w["dims"], U, kappa, w["csw"], bc_t=w["bc_t"])
+    return w, c, op
+
+
+def test_solve_small_workload_matches_dense_lu(pkg):
+    """4^4, kappa 0.12, c_SW 1.0, four Z4 sources, no preconditioner."""
+    w, c, op = _workload_ctx(pkg, "lat4_L4_z4")
+    B = wi.z4_block(op.V, w["L"], w["source_seed"])
+    X, info = c.solve(_dev(B), tol=w["tol"], j=0)
+    assert info["status"] == "converged", info
+    Xh = _host(X)
+    Bm = op.block_to_mat(B)
+    Xm = op.block_to_mat(Xh)
+    assert np.max(true_residual(op.A_mat, Bm, Xm)) <= 1e-12
+    assert np.max(info["true_residual"]) <= 1e-12
+    Xd = np.linalg.solve(op.dense(), Bm)
+    assert _rel(Xm, Xd) < 1e-10
+    assert info["mvm_paper"] == 2 * info["iterations"] + 1 or info["restarts"] > 0
+    # same iteration as the oracle's: iteration counts agree closely
+    Xo, io = block_bicggr(op.A_mat, lambda m: m.copy(), Bm, w["tol"], 0)
+    assert abs(io["iterations"] - info["iterations"]) <= 3
+    c.close()
+
+
+@pytest.mark.parametrize("k", [1, 2, 3])
+def test_solve_first_iterations_match_oracle(pkg, k):
+    """After k outer iterations the GPU iterate equals the oracle's (same steps, FP64 rounding only)."""
+    dims = (4, 4, 4, 6)
+    U = wi.random_links(dims, 0.3, 120)
+    op = WilsonClover(dims, U, 0.125, 1.4)
+    c = _ctx(pkg, dims, U, 0.125, 1.4)
+    B = wi.z4_block(op.V, 5, 121)
+    for j in (0, 3):
+        X, info = c.solve(_dev(B), tol=1e-30, j=j, max_iter=k, max_restarts=0)
+        assert info["status"] == "not_converged" and info["iterations"] == k
+        Bm = op.block_to_mat(B)
+        from oracle.jacobi import jacobi_mat
+        Xo, io = block_bicggr(op.A_mat, lambda m: jacobi_mat(op, m, j), Bm, 1e-30, j, max_iter=k)
+        assert io["iterations"] == k
+        assert _rel(op.block_to_mat(_host(X)), Xo) < 1e-12
+        assert info["mvm_paper"] == io["mvm_paper"]
+    c.close()
+
+
+def test_solve_point_sources_jacobi_oracle_residual(pkg):
+    """8^3 x 16, kappa 0.135, c_SW 1.6, twelve point sources, Jacobi j = 4 and 12."""
+    w, c, op = _workload_ctx(pkg, "lat8x16_L12_point")
+    B = wi.point_block(op.V, 12)
+    Bm = op.block_to_mat(B)
+    for j in (4, 12):
+        X, info = c.solve(_dev(B), tol=1e-12, j=j)
+        assert info["status"] == "converged", info
+        assert np.max(info["true_residual"]) <= 1e-12
+        # independent check with the oracle's operator
+        tr = true_residual(op.A_mat, Bm, op.block_to_mat(_host(X)))
+        assert np.max(tr) <= 1e-12
+        if info["restarts"] == 0:
+            assert info["mvm_paper"] == 2 * (j + 1) * info["iterations"] + 1
+    c.close()
+
+
+def test_solve_failure_paths(pkg):
+    dims = (4, 4, 4, 4)
+    U = wi.random_links(dims, 0.3, 130)
+    c = _ctx(pkg, dims, U, 0.12, 1.0)
+    V = wi.volume(dims)
+    b = wi.z4_block(V, 1, 131)
+    X, info = c.solve(_dev(np.concatenate([b, b])), j=1)
+    assert info["status"] == "breakdown"
+    assert np.all(np.isfinite(_host(X)))
+    Bz = wi.z4_block(V, 2, 132)
+    Bz[1] = 0
+    with pytest.raises(pkg.WDError):
+        c.solve(_dev(Bz))
+    X, info = c.solve(_dev(wi.z4_block(V, 2, 133)), j=0, max_iter=3, max_restarts=0)
+    assert info["status"] == "not_converged" and info["iterations"] == 3
+    X, info = c.solve(_dev(wi.z4_block(V, 2, 133)), j=0, diverge_at=1e-3)
+    assert info["status"] == "diverged"
+    c.close()
+
+
+def test_solve_deterministic(pkg):
+    dims = (4, 4, 4, 8)
+    U = wi.random_links(dims, 0.3, 140)
+    c = _ctx(pkg, dims, U, 0.13, 1.6)
+    B = _dev(wi.point_block(wi.volume(dims), 6))
+    X1, i1 = c.solve(B, j=4)
+    X1 = _host(X1)
+    X2, i2 = c.solve(B, j=4)
+    assert np.array_equal(X1, _host(X2)) and i1["iterations"] == i2["iterations"]
+    c.close()
+
+
+# ---------------------------------------------------------------- full-size spot checks
+
+@pytest.fixture(scope="module")
+def big(pkg):
+    """32^3 x 64 lattice with twelve columns: the bandwidth workload."""
+    w = wi.workload("lat32x64_L12_point")
+    U = wi.random_links(w["dims"], w["eps"], w["link_seed"])
+    c = _ctx(pkg, w["dims"], U, w["kappa"], w["csw"], w["bc_t"], max_L=12)
+    yield w, c, U
+    c.close()
+
+
+def _sample_sites(V, n=24, seed=7):
+    rng = np.random.default_rng(seed)
+    return sorted(set([0, V - 1] + list(rng.integers(0, V, n))))
+
+
+def test_full_size_apply_sampled(pkg, big):
+    w, c, U = big
+    V = wi.volume(w["dims"])
+    g = torch.Generator(device="cuda").manual_seed(5)
+    X = torch.complex(torch.randn((12, 12, V), generator=g, device="cuda", dtype=torch.float64),
+                      torch.randn((12, 12, V), generator=g, device="cuda", dtype=torch.float64))
+    Y = c.apply(X)
+    so = SiteOperator(w["dims"], U, w["kappa"], w["csw"], w["bc_t"])
+    sites = _sample_sites(V)
+    need = sorted(set(sites) | {n for s in sites for (_, _, n, _) in so.neighbours(s)})
+    idx = torch.tensor(need, device="cuda")
+    Xs = X[:, :, idx].cpu().numpy()
+    pos = {s: i for i, s in enumerate(need)}
+    Ys = Y[:, :, torch.tensor(sites, device="cuda")].cpu().numpy()
+    for k, s in enumerate(sites):
+        ref = so.apply_at(s, lambda t: Xs[:, :, pos[t]].T)       # (12, L)
+        assert _maxrel(Ys[:, :, k].T, ref) < 1e-13
+
+
+def test_full_size_jacobi_two_sweeps_sampled(pkg, big):
+    """Z = T^-1 (R + kappa H T^-1 R) at sampled sites (j = 2 reaches one hop)."""
+    w, c, U = big
+    V = wi.volume(w["dims"])
+    g = torch.Generator(device="cuda").manual_seed(6)
+    R = torch.complex(torch.randn((12, 12, V), generator=g, device="cuda", dtype=torch.float64),
+                      torch.randn((12, 12, V), generator=g, device="cuda", dtype=torch.float64))
+    Z = c.jacobi(R, 2)
+    so = SiteOperator(w["dims"], U, w["kappa"], w["csw"], w["bc_t"])
+    sites = _sample_sites(V, 8, 9)
+    need = sorted(set(sites) | {n for s in sites for (_, _, n, _) in so.neighbours(s)})
+    Rs = R[:, :, torch.tensor(need, device="cuda")].cpu().numpy()
+    pos = {s: i for i, s in enumerate(need)}
+    Zs = Z[:, :, torch.tensor(sites, device="cuda")].cpu().numpy()
+    Tinv = {s: np.linalg.inv(so.T(s)) for s in need}
+    for k, s in enumerate(sites):
+        g1 = lambda t: Tinv[t] @ Rs[:, :, pos[t]].T             # noqa: E731
+        ref = Tinv[s] @ (Rs[:, :, pos[s]].T + w["kappa"] * so.hop_at(s, g1))
+        assert _maxrel(Zs[:, :, k].T, ref) < 1e-13
