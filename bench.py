@@ -1,0 +1,226 @@
+#!/usr/bin/env python3
+"""Throughput benchmark of the Jacobi-preconditioned block BiCGGR hot path.
+
+One step = one complete solve of A X = B for one batch of L right-hand sides
+(point sources) to a relative residual of 1e-12 in every column: every
+kernel of the hot path (operator, clover, Jacobi sweeps, Gram products, L x L
+solves, block updates, driver) runs in it.  Inputs are resident in HBM before
+the timed region starts.
+
+Printed JSON line (one, from rank 0):
+  value        algorithmic HBM bytes of all kernels of the timed solves / time (GB/s)
+  s_per_rhs    seconds per right-hand side of the timed solves
+  roofline     the dominant kernel (the FP64 Jacobi sweep, 2j-2 of the 2j+2
+               hopping-kernel launches per outer iteration), timed with HIP
+               events around back-to-back launches on the library's stream
+  dslash       the same measurement for the operator kernel Y = A X
+  solves       one solve per inner precision (FP64, FP32, BF16 Jacobi) for
+               the time-to-solution comparison
+  cpu_baseline the FP64 oracle on a bounded sample of the same workload
+"""
+
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import resource
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0   # MI355X HBM3E
+
+
+def parse():
+    p = argparse.ArgumentParser()
+    p.add_argument("--gpus", type=int, default=1)
+    p.add_argument("--steps", type=int, default=2)
+    p.add_argument("--warmup", type=int, default=1)
+    p.add_argument("--workload", default="lat32x64_L12_point")
+    p.add_argument("--j", type=int, default=12)
+    p.add_argument("--kappa", type=float, default=None)
+    p.add_argument("--hop-reps", type=int, default=20)
+    p.add_argument("--no-compare", action="store_true", help="skip the per-precision solve comparison")
+    p.add_argument("--no-cpu-baseline", action="store_true")
+    return p.parse_args()
+
+
+def src_hash():
+    h = hashlib.sha256()
+    d = os.path.join(ROOT, "paper_0907_3261_amd", "csrc")
+    for f in sorted(os.listdir(d)):
+        with open(os.path.join(d, f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def traffic_from_profiles(kernel_key: str):
+    """HBM bytes per launch measured by rocprofv3 counters, if taken on the current sources."""
+    path = os.path.join(ROOT, "profiles", "traffic.json")
+    if not os.path.exists(path):
+        return None
+    try:
+        d = json.load(open(path))
+        e = d.get(kernel_key)
+        if e and e.get("src_hash") == src_hash():
+            return e.get("bytes_per_launch")
+    except Exception:
+        return None
+    return None
+
+
+def time_hop(ctx, torch, V, L, mode, reps):
+    """Average duration of one hopping-kernel launch (mode 0: A X, 1: Jacobi sweep)."""
+    g = torch.Generator(device="cuda").manual_seed(11)
+    X = torch.complex(torch.randn((L, 12, V), generator=g, device="cuda", dtype=torch.float64),
+                      torch.randn((L, 12, V), generator=g, device="cuda", dtype=torch.float64))
+    R = torch.complex(torch.randn((L, 12, V), generator=g, device="cuda", dtype=torch.float64),
+                      torch.randn((L, 12, V), generator=g, device="cuda", dtype=torch.float64))
+    Y = torch.empty_like(X)
+    ctx.hop_repeat(X, Y, 3, mode, R)
+    st = ctx.stream
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record(st)
+    ctx.hop_repeat(X, Y, reps, mode, R)
+    e1.record(st)
+    e1.synchronize()
+    del X, R, Y
+    return e0.elapsed_time(e1) / reps
+
+
+def cpu_baseline(w, kappa):
+    """Oracle A X on a 32 x 32 x 32 x 2 slab of the workload's ensemble, twelve columns."""
+    import numpy as np
+    import wdinputs as wi
+    from oracle import WilsonClover
+    dims = (w["dims"][0], w["dims"][1], w["dims"][2], 2)
+    U = wi.random_links(dims, w["eps"], w["link_seed"])
+    op = WilsonClover(dims, U, kappa, w["csw"], bc_t=w["bc_t"])
+    L = 12
+    X = op.from_block(wi.gaussian_block(op.V, L, 3))
+    reps = 3
+    c0 = time.process_time()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        op.apply_A(X)
+    wall = time.perf_counter() - t0
+    cpu = time.process_time() - c0
+    gbs = reps * op.V * (1152 + 384 * L) / wall / 1e9
+    return {"value": round(gbs, 4), "unit": "GB/s", "cores": max(1, round(cpu / wall)), "kind": "oracle",
+            "sample": f"{reps} FP64 applications of A (numpy oracle) on a {dims[0]}x{dims[1]}x{dims[2]}x{dims[3]} "
+                      f"slab of the same link ensemble, L={L}, {wall:.1f} s wall; algorithmic bytes per "
+                      f"site as for the GPU operator kernel",
+            "host_cpus": len(os.sched_getaffinity(0))}
+
+
+def main():
+    a = parse()
+    if a.gpus != 1:
+        print(f"bench.py runs on one GPU only; --gpus {a.gpus} is not supported by this build "
+              "(the multi-GPU domain decomposition is a design, not code).", file=sys.stderr)
+        sys.exit(2)
+    import numpy as np
+    import torch
+    import paper_0907_3261_amd as pkg
+    import wdinputs as wi
+
+    pkg.load()
+    w = wi.workload(a.workload)
+    kappa = a.kappa if a.kappa is not None else (w["kappa"][-1] if isinstance(w["kappa"], tuple) else w["kappa"])
+    L = w["L"] if isinstance(w["L"], int) else max(w["L"])
+    V = wi.volume(w["dims"])
+    t_setup = time.time()
+    U = wi.random_links(w["dims"], w["eps"], w["link_seed"])
+    ctx = pkg.Context(w["dims"], bc_t=w["bc_t"], max_L=L)
+    ctx.set_links(U)
+    ctx.set_params(kappa, w["csw"])
+    del U
+    B = torch.from_numpy(wi.source_block(w["source"], V, L, w["source_seed"])).cuda()
+    torch.cuda.synchronize()
+    print(f"[bench] setup {time.time() - t_setup:.1f}s  workload {a.workload} V={V} L={L} kappa={kappa}",
+          file=sys.stderr, flush=True)
+
+    st = ctx.stream
+    for i in range(a.warmup):
+        X, info = ctx.solve(B, tol=w["tol"], j=a.j)
+        print(f"[bench] warmup {i}: {info['status']} k={info['iterations']} {info['seconds']:.2f}s",
+              file=sys.stderr, flush=True)
+    torch.cuda.synchronize()
+    infos = []
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record(st)
+    for i in range(a.steps):
+        X, info = ctx.solve(B, tol=w["tol"], j=a.j)
+        infos.append(info)
+        print(f"[bench] step {i}: {info['status']} k={info['iterations']} {info['seconds']:.2f}s", file=sys.stderr,
+              flush=True)
+    e1.record(st)
+    e1.synchronize()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1)
+    ok = all(i["status"] == "converged" and float(np.max(i["true_residual"])) <= w["tol"] for i in infos)
+    bytes_total = sum(i["bytes_alg"] for i in infos)
+    value = bytes_total / (ms / 1e3) / 1e9
+    ms_step = ms / a.steps
+
+    # dominant kernel: the Jacobi sweep; also the operator kernel
+    ms_sweep = time_hop(ctx, torch, V, L, 1, a.hop_reps)
+    ms_apply = time_hop(ctx, torch, V, L, 0, a.hop_reps)
+    b_sweep = V * (1152 + 576 * L)
+    b_apply = V * (1152 + 384 * L)
+    ach = b_sweep / (ms_sweep / 1e3) / 1e9
+    roof = {"bound": "hbm", "achieved": round(ach, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": round(ach / HBM_PEAK_GBS, 4), "traffic": traffic_from_profiles("jacobi_sweep_f64"),
+            "kernel": f"k_hop<StF64,StF64,CT,JBLOCK> (Jacobi sweep, L={L})",
+            "avg_launch_ms": round(ms_sweep, 4), "alg_bytes_per_launch": b_sweep}
+    ach_a = b_apply / (ms_apply / 1e3) / 1e9
+    dslash = {"achieved": round(ach_a, 1), "frac": round(ach_a / HBM_PEAK_GBS, 4), "unit": "GB/s",
+              "avg_launch_ms": round(ms_apply, 4), "alg_bytes_per_launch": b_apply,
+              "traffic": traffic_from_profiles("apply_f64")}
+
+    solves = {}
+    if not a.no_compare:
+        Xref = None
+        for prec in ("f64", "f32", "bf16"):
+            torch.cuda.synchronize()
+            X, info = ctx.solve(B, tol=w["tol"], j=a.j, prec_inner=prec)
+            torch.cuda.synchronize()
+            if prec == "f64":
+                Xref = X.clone()
+                dx = 0.0
+            else:
+                dx = float(torch.linalg.vector_norm(X - Xref) / torch.linalg.vector_norm(Xref))
+            solves[f"jacobi{a.j}_{prec}"] = {
+                "status": info["status"], "iterations": info["iterations"], "restarts": info["restarts"],
+                "s_per_rhs": round(info["seconds"] / L, 5), "true_residual_max": float(np.max(info["true_residual"])),
+                "mvm_paper_per_col": int(info["mvm_paper"]), "rel_diff_vs_f64": dx}
+            print(f"[bench] compare {prec}: {solves[f'jacobi{a.j}_{prec}']}", file=sys.stderr, flush=True)
+
+    cpu = None if a.no_cpu_baseline else cpu_baseline(w, kappa)
+    ctx.close()
+    line = {
+        "metric": "Dslash GB/s (%HBM peak); s/RHS to 1e-12, mixed+learned vs FP64 plain",
+        "value": round(value, 1), "unit": "GB/s", "n_gpus": 1, "steps": a.steps, "warmup": a.warmup,
+        "ms_per_step": round(ms_step, 3), "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f64", "data": "synthetic",
+        "config": {"workload": a.workload, "dims": list(w["dims"]), "L": L, "kappa": kappa, "csw": w["csw"],
+                   "eps": w["eps"], "sources": w["source"], "j": a.j, "tol": w["tol"],
+                   "step": "one complete solve of the L right-hand sides"},
+        "pct_hbm_peak": round(value / HBM_PEAK_GBS * 100, 2),
+        "s_per_rhs": round(ms_step / 1e3 / L, 5),
+        "converged": ok,
+        "iterations": [i["iterations"] for i in infos],
+        "roofline": roof, "dslash": dslash, "solves": solves, "cpu_baseline": cpu,
+        "src_hash": src_hash(),
+    }
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -48,12 +48,13 @@ __device__ __forceinline__ double wave_sum(double v) {
 }
 
 // Sum the per-wave 16x16 tiles of the workgroup and write the partial tile.
-// MFMA output layout: lane l holds D[4*(l/16) + v][l % 16], v = 0..3.
+// Output layout of v_mfma_f64_16x16x4f64 (measured): lane l holds
+// D[l/16 + 4 v][l % 16] in accumulator element v = 0..3.
 __device__ __forceinline__ void gram_store(const GramAcc& acc, double2* __restrict__ out, double2* sh) {
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
     const int j = lane & 15, rg = lane >> 4;
 #pragma unroll
-    for (int v = 0; v < 4; ++v) sh[w * 256 + (4 * rg + v) * 16 + j] = make_double2(acc.re[v], acc.im[v]);
+    for (int v = 0; v < 4; ++v) sh[w * 256 + (rg + 4 * v) * 16 + j] = make_double2(acc.re[v], acc.im[v]);
     __syncthreads();
     const int e = threadIdx.x;  // kWG == 256 entries
     double2 s = sh[e];

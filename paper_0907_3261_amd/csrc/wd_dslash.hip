@@ -156,28 +156,24 @@ __device__ __forceinline__ void hop_all(cx<typename S::R> (&acc)[CT][12], const 
 
 template <class SY, typename R>
 __device__ __forceinline__ void store_out(typename SY::P* base, uint32_t boff, cx<R> v) {
-    SY::stb(base, boff, cx<typename SY::R>{(typename SY::R)v.re, (typename SY::R)v.im});
+    SY::stb_nt(base, boff, cx<typename SY::R>{(typename SY::R)v.re, (typename SY::R)v.im});
 }
 
 // SF: storage of links, clover and the X / Rh inputs (and compute type);
 // SY: storage of the output.
 template <class SF, class SY, int CT, int MODE>
 __global__ void __launch_bounds__(256)
-    k_hop(const Geom g, const typename SF::P* __restrict__ Uk, const typename SF::P* __restrict__ Cl,
+    k_hop(const Geom g, const SiteMap sm, const typename SF::P* __restrict__ Uk, const typename SF::P* __restrict__ Cl,
           const typename SF::P* __restrict__ X, const typename SF::P* __restrict__ Rh, typename SY::P* __restrict__ Y,
-          const int col_begin, const int ntiles, const int tiles_per_group, const int groups) {
+          const int col_begin, const int ntiles) {
     using R = typename SF::R;
     using PF = typename SF::P;
     using PY = typename SY::P;
-    const int lin = xcd_remap(blockIdx.x, gridDim.x);
-    const int site_blk = lin / groups;
+    const int s = map_site(g, sm, blockIdx.x, threadIdx.x);
     // blockDim.x == 64: threadIdx.y is the same for the whole wavefront
-    const int ty = __builtin_amdgcn_readfirstlane(threadIdx.y);
-    const int tile = (lin % groups) * tiles_per_group + ty;
-    if (tile >= ntiles) return;
+    const int tile = __builtin_amdgcn_readfirstlane(threadIdx.y);
+    if (tile >= ntiles || s < 0) return;
     const int c0 = col_begin + tile * CT;
-    const int s = site_blk * 64 + threadIdx.x;
-    if (s >= g.V) return;
     const size_t V = g.V;
     const size_t cs = 12 * V;  // column stride
 
@@ -224,7 +220,7 @@ __global__ void __launch_bounds__(256)
         for (int c = 0; c < CT; ++c) {
 #pragma unroll
             for (int k = 0; k < 12; ++k)
-                acc[c][k] = SF::ldb(Rc + (size_t)c * cs + (size_t)k * V, o_s);
+                acc[c][k] = SF::ldb_nt(Rc + (size_t)c * cs + (size_t)k * V, o_s);
         }
     }
 
@@ -345,7 +341,7 @@ int tile_cols(int L) {
         return e ? std::atoi(e) : 0;
     }();
     if (forced >= 1 && forced <= 4) return forced < L ? forced : L;
-    if (L <= 4) return 1;
+    if (L <= 2) return 1;
     if (L <= 8) return 2;
     if (L <= 12) return 3;
     return 4;
@@ -354,15 +350,14 @@ int tile_cols(int L) {
 template <class SF, class SY, int MODE, int CT>
 hipError_t launch_hop_ct(const Geom& g, const void* Uk, const void* Cl, const void* X, const void* Rh, void* Y,
                          int col_begin, int ntiles, hipStream_t s) {
-    // up to 4 column tiles share one workgroup (and so the links in cache)
-    const int groups = (ntiles + 3) / 4;
-    const int tpg = (ntiles + groups - 1) / groups;
-    const int sblk = (g.V + 63) / 64;
-    dim3 block(64, tpg), grid(sblk * groups);
+    if (ntiles > 4) return hipErrorInvalidValue;  // at most 4 wavefronts (256 threads) per site tile
+    const double bytes_site = 12.0 * CT * ntiles * sizeof(typename SF::P) + 72.0 * sizeof(typename SF::P);
+    const SiteMap sm = make_site_map(g, bytes_site);
+    dim3 block(64, ntiles), grid(sm.nblk);
     using PF = typename SF::P;
     using PY = typename SY::P;
-    k_hop<SF, SY, CT, MODE><<<grid, block, 0, s>>>(g, (const PF*)Uk, (const PF*)Cl, (const PF*)X, (const PF*)Rh,
-                                                   (PY*)Y, col_begin, ntiles, tpg, groups);
+    k_hop<SF, SY, CT, MODE><<<grid, block, 0, s>>>(g, sm, (const PF*)Uk, (const PF*)Cl, (const PF*)X, (const PF*)Rh,
+                                                   (PY*)Y, col_begin, ntiles);
     return hipGetLastError();
 }
 
@@ -378,13 +373,18 @@ hipError_t launch_hop_cols(const Geom& g, const void* Uk, const void* Cl, const 
     }
 }
 
-// L columns: full tiles of CT columns, then one launch for the remainder.
+// L columns: launches of up to four tiles of CT columns, then one launch for
+// the remainder (fewer than CT columns).
 template <class SF, class SY, int MODE>
 hipError_t launch_hop_t(const Geom& g, const void* Uk, const void* Cl, const void* X, const void* Rh, void* Y, int L,
                         hipStream_t s) {
     const int CT = tile_cols(L);
     const int full = L / CT, rem = L % CT;
-    hipError_t e = launch_hop_cols<SF, SY, MODE>(g, Uk, Cl, X, Rh, Y, CT, 0, full, s);
+    hipError_t e = hipSuccess;
+    for (int t0 = 0; t0 < full && e == hipSuccess; t0 += 4) {
+        const int nt = full - t0 < 4 ? full - t0 : 4;
+        e = launch_hop_cols<SF, SY, MODE>(g, Uk, Cl, X, Rh, Y, CT, t0 * CT, nt, s);
+    }
     if (e != hipSuccess || rem == 0) return e;
     return launch_hop_cols<SF, SY, MODE>(g, Uk, Cl, X, Rh, Y, rem, full * CT, 1, s);
 }

@@ -73,11 +73,29 @@ __host__ __device__ __forceinline__ void cfmac(cx<R>& a, cx<R> b, cx<R> c) {
     }                                                                                   \
     __device__ __forceinline__ static void stb(P* base, uint32_t boff, cx<R> v) {       \
         st(reinterpret_cast<P*>(reinterpret_cast<char*>(base) + boff), 0, v);          \
+    }                                                                                   \
+    __device__ __forceinline__ static cx<R> ldb_nt(const P* base, uint32_t boff) {      \
+        return ld_nt(reinterpret_cast<const P*>(reinterpret_cast<const char*>(base) + boff)); \
+    }                                                                                   \
+    __device__ __forceinline__ static void stb_nt(P* base, uint32_t boff, cx<R> v) {    \
+        st_nt(reinterpret_cast<P*>(reinterpret_cast<char*>(base) + boff), v);          \
     }
+typedef double wd_dvec2 __attribute__((ext_vector_type(2)));
+typedef float wd_fvec2 __attribute__((ext_vector_type(2)));
+
+// Non-temporal ("streaming") accesses are used for data touched once per
+// kernel (outputs, right-hand sides) so they do not evict reused neighbours.
 struct StF64 {
     using R = double;
     using P = double2;
     static constexpr int bytes = 16;
+    __device__ __forceinline__ static cx<R> ld_nt(const P* p) {
+        const wd_dvec2 v = __builtin_nontemporal_load(reinterpret_cast<const wd_dvec2*>(p));
+        return {v.x, v.y};
+    }
+    __device__ __forceinline__ static void st_nt(P* p, cx<R> v) {
+        __builtin_nontemporal_store(wd_dvec2{v.re, v.im}, reinterpret_cast<wd_dvec2*>(p));
+    }
     __device__ __forceinline__ static cx<R> ld(const P* p, size_t i) {
         P v = p[i];
         return {v.x, v.y};
@@ -91,6 +109,13 @@ struct StF32 {
     using R = float;
     using P = float2;
     static constexpr int bytes = 8;
+    __device__ __forceinline__ static cx<R> ld_nt(const P* p) {
+        const wd_fvec2 v = __builtin_nontemporal_load(reinterpret_cast<const wd_fvec2*>(p));
+        return {v.x, v.y};
+    }
+    __device__ __forceinline__ static void st_nt(P* p, cx<R> v) {
+        __builtin_nontemporal_store(wd_fvec2{v.re, v.im}, reinterpret_cast<wd_fvec2*>(p));
+    }
     __device__ __forceinline__ static cx<R> ld(const P* p, size_t i) {
         P v = p[i];
         return {v.x, v.y};
@@ -111,6 +136,13 @@ struct StBF16 {
     using R = float;
     using P = uint32_t;
     static constexpr int bytes = 4;
+    __device__ __forceinline__ static cx<R> ld_nt(const P* p) {
+        const uint32_t v = __builtin_nontemporal_load(p);
+        return {__uint_as_float(v << 16), __uint_as_float(v & 0xffff0000u)};
+    }
+    __device__ __forceinline__ static void st_nt(P* p, cx<R> v) {
+        __builtin_nontemporal_store(f32_to_bf16_rne(v.re) | (f32_to_bf16_rne(v.im) << 16), p);
+    }
     __device__ __forceinline__ static cx<R> ld(const P* p, size_t i) {
         uint32_t v = p[i];
         return {__uint_as_float(v << 16), __uint_as_float(v & 0xffff0000u)};
@@ -152,6 +184,64 @@ __device__ __forceinline__ int xcd_remap(int b, int nb) {
     const int q = nb / nx, r = nb % nx;
     const int x = b % nx, i = b / nx;
     return x * q + (x < r ? x : r) + i;
+}
+
+// Site tiles of the stencil kernels.  The hardware hands workgroup b to
+// XCD b % 8.  XCD k owns the sub-lattice Lx x [y-range] x [z-range] x Lt
+// (y split ny ways, z split nz = 8 / ny ways) and walks it t-slice by
+// t-slice, z-plane by z-plane, 64-site tiles of its (x, y) rows fastest.  A
+// site's y-neighbour was then read one row earlier and its z-neighbour one
+// plane (Lx * Ly / ny sites) earlier, both in the XCD's L2 when the plane is
+// small enough, which is what ny is chosen for; its t-neighbour was read one
+// slab-slice earlier and is served by the shared MALL, as are the faces
+// between XCDs, whose neighbours are processed at the same time.  Lattices
+// with Lz * Ly too small for the split use contiguous site ranges.
+struct SiteMap {
+    int mode;   // 1: XCD sub-lattices, 0: contiguous ranges
+    int ny;     // y split
+    int nz;     // z split
+    int tpp;    // 64-site tiles per plane of a sub-lattice (max over XCDs)
+    int nblk;   // workgroups in the grid
+};
+
+// Site of this lane, or -1.
+__device__ __forceinline__ int map_site(const Geom& g, const SiteMap& m, int b, int lane) {
+    if (m.mode == 1) {
+        const int k = b & 7, i = b >> 3;
+        const int ky = k % m.ny, kz = k / m.ny;
+        const int y0 = (ky * g.ly) / m.ny, ny = ((ky + 1) * g.ly) / m.ny - y0;
+        const int z0 = (kz * g.lz) / m.nz, nz = ((kz + 1) * g.lz) / m.nz - z0;
+        const int plane = i / m.tpp, tip = i - plane * m.tpp;
+        if (plane >= nz * g.lt) return -1;
+        const int t = plane / nz, z = z0 + (plane - t * nz);
+        const int xy = tip * 64 + lane;
+        if (xy >= g.lx * ny) return -1;
+        const int y = y0 + xy / g.lx, x = xy - (xy / g.lx) * g.lx;
+        return x + g.lx * (y + g.ly * (z + g.lz * t));
+    }
+    const int lin = xcd_remap(b, m.nblk);
+    const int s = lin * 64 + lane;
+    return s < g.V ? s : -1;
+}
+
+// bytes_site: bytes per site a stencil launch keeps reusing (input block
+// vector plus links and clover)
+inline SiteMap make_site_map(const Geom& g, double bytes_site) {
+    SiteMap m{};
+    const double budget = 2.0 * 1024 * 1024;
+    for (int ny = 1; ny <= 8; ny *= 2) {
+        const int nz = 8 / ny;
+        if (g.ly < ny || g.lz < nz) continue;
+        const int rows = (g.ly + ny - 1) / ny;
+        m.mode = 1;
+        m.ny = ny;
+        m.nz = nz;
+        m.tpp = (g.lx * rows + 63) / 64;
+        m.nblk = 8 * ((g.lz + nz - 1) / nz) * g.lt * m.tpp;
+        if (g.lx * rows * bytes_site <= budget) break;  // else try a finer y split
+    }
+    if (m.mode == 0) m.nblk = (g.V + 63) / 64;
+    return m;
 }
 
 // ---------------------------------------------------------------------------

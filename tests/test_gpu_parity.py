@@ -66,7 +66,9 @@ def _maxrel(a, b):
     return np.max(np.abs(a - b)) / np.max(np.abs(b))
 
 
-CASES = [((4, 4, 4, 4), 0), ((3, 4, 5, 6), 1), ((2, 2, 2, 2), 0), ((8, 6, 4, 10), 1)]
+# (16, 8, 4, 4) and (8, 16, 8, 3) take the pencil tile map (8 x 8 x 1 and 8 x 8 x 2 pencils)
+CASES = [((4, 4, 4, 4), 0), ((3, 4, 5, 6), 1), ((2, 2, 2, 2), 0), ((8, 6, 4, 10), 1), ((16, 8, 4, 4), 1),
+         ((8, 16, 8, 3), 0)]
 
 
 # ---------------------------------------------------------------- clover setup
@@ -153,8 +155,8 @@ def test_apply_rejects_bad_arguments(pkg):
 
 @pytest.mark.parametrize("kind", [0, 1])
 @pytest.mark.parametrize("j", [0, 1, 2, 5, 12])
-def test_jacobi_matches_oracle(pkg, kind, j):
-    dims = (4, 4, 6, 4)
+@pytest.mark.parametrize("dims", [(4, 4, 6, 4), (8, 16, 8, 3)])
+def test_jacobi_matches_oracle(pkg, kind, j, dims):
     U = wi.random_links(dims, 0.3, 109)
     op = WilsonClover(dims, U, 0.13, 1.6, bc_t=1, jacobi_kind="block" if kind == 0 else "point")
     c = _ctx(pkg, dims, U, 0.13, 1.6, 1, kind=kind)

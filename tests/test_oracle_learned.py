@@ -1,0 +1,117 @@
+"""Pins of the oracle's learned linear preconditioner: reduction to the Wilson
+hopping term, identity initialisation, the adjoint identity, gauge
+covariance, and central finite differences of the loss."""
+
+import numpy as np
+import pytest
+
+import wdinputs as wi
+from oracle import WilsonClover, gammas
+from oracle import learned as ln
+
+
+def _op(dims=(2, 2, 2, 4), kappa=0.11, csw=1.0, bc_t=1, seed=9):
+    return WilsonClover(dims, wi.random_links(dims, 0.5, seed), kappa, csw, bc_t=bc_t)
+
+
+def _rand_theta(rng, scale=0.3):
+    th = ln.identity_theta()
+    th += scale * (rng.standard_normal(th.shape) + 1j * rng.standard_normal(th.shape))
+    return th
+
+
+def test_identity_theta_is_identity():
+    op = _op()
+    f = op.from_block(wi.gaussian_block(op.V, 2, 1))
+    assert np.array_equal(ln.forward(op, ln.identity_theta(), f), f)
+
+
+@pytest.mark.parametrize("bc_t", [0, 1])
+def test_layer_reduces_to_wilson_hop(bc_t):
+    """W_0 = 1, W_{+mu} = kappa (1 - g_mu), W_{-mu} = kappa (1 + g_mu): the layer is 1 + kappa H."""
+    op = _op(dims=(4, 2, 2, 4), kappa=0.13, csw=0.0, bc_t=bc_t)
+    g = gammas()
+    W = np.zeros((9, 4, 4), dtype=np.complex128)
+    W[0] = np.eye(4)
+    for mu in range(4):
+        W[1 + 2 * mu] = op.kappa * (np.eye(4) - g[mu])
+        W[2 + 2 * mu] = op.kappa * (np.eye(4) + g[mu])
+    f = op.from_block(wi.gaussian_block(op.V, 3, 2))
+    lhs = ln.layer(op, W, f)
+    rhs = f + op.kappa * op.hop(f)
+    assert np.max(np.abs(lhs - rhs)) < 1e-14
+    # at c_SW = 0 this is 2 - A
+    assert np.max(np.abs(lhs - (2 * f - op.apply_A(f)))) < 1e-14
+
+
+def test_adjoint_identity():
+    rng = np.random.default_rng(3)
+    op = _op(dims=(2, 4, 2, 4))
+    W = _rand_theta(rng)[0]
+    phi = op.from_block(wi.gaussian_block(op.V, 2, 4))
+    psi = op.from_block(wi.gaussian_block(op.V, 2, 5))
+    lhs = np.vdot(phi, ln.layer(op, W, psi))
+    rhs = np.vdot(ln.layer(op, ln.adjoint_weights(W), phi), psi)
+    assert abs(lhs - rhs) / abs(lhs) < 1e-13
+
+
+def test_gauge_covariance_and_linearity():
+    rng = np.random.default_rng(6)
+    dims = (2, 2, 4, 2)
+    U = wi.random_links(dims, 0.5, 7)
+    gx = wi.random_gauge_transform(dims, 1.0, 8)
+    V = wi.volume(dims)
+    lx, ly, lz, lt = dims
+    Ug = np.empty_like(U)
+    for s in range(V):
+        c = [s % lx, (s // lx) % ly, (s // (lx * ly)) % lz, s // (lx * ly * lz)]
+        for mu in range(4):
+            cn = list(c)
+            cn[mu] = (cn[mu] + 1) % dims[mu]
+            s2 = cn[0] + lx * (cn[1] + ly * (cn[2] + lz * cn[3]))
+            Ug[mu, s] = gx[s] @ U[mu, s] @ gx[s2].conj().T
+    op = WilsonClover(dims, U, 0.1, 1.0)
+    opg = WilsonClover(dims, Ug, 0.1, 1.0)
+    th = _rand_theta(rng)
+    f = op.from_block(wi.gaussian_block(V, 2, 9))
+    h = op.from_block(wi.gaussian_block(V, 2, 10))
+    G = gx.reshape(op.shape + (3, 3))
+
+    def gm(x):
+        return np.einsum("...ab,...sbl->...sal", G, x)
+
+    out = ln.forward(opg, th, gm(f))
+    assert np.max(np.abs(out - gm(ln.forward(op, th, f)))) < 1e-13
+    lin = ln.forward(op, th, 2.0 * f - 3j * h) - (2.0 * ln.forward(op, th, f) - 3j * ln.forward(op, th, h))
+    assert np.max(np.abs(lin)) < 1e-12
+
+
+def test_gradient_matches_central_differences():
+    rng = np.random.default_rng(11)
+    op = _op(dims=(2, 2, 2, 2), bc_t=1)
+    th = _rand_theta(rng, 0.2)
+    R = op.from_block(wi.gaussian_block(op.V, 3, 12))
+    E = op.from_block(wi.gaussian_block(op.V, 3, 13))
+    lv, G = ln.grad(op, th, R, E)
+    assert abs(lv - ln.loss(op, th, R, E)) < 1e-12
+    h = 1e-6
+    for _ in range(12):
+        idx = tuple(rng.integers(0, n) for n in th.shape)
+        for part in (1.0, 1j):
+            tp = th.copy()
+            tm = th.copy()
+            tp[idx] += h * part
+            tm[idx] -= h * part
+            fd = (ln.loss(op, tp, R, E) - ln.loss(op, tm, R, E)) / (2 * h)
+            an = G[idx].real if part == 1.0 else G[idx].imag
+            assert abs(fd - an) <= 1e-7 * max(1.0, abs(an))
+
+
+def test_training_lowers_loss():
+    op = _op(dims=(4, 4, 2, 2), kappa=0.1, csw=1.0, bc_t=0)
+    E = op.from_block(wi.gaussian_block(op.V, 8, 14))
+    R = op.apply_A(E)
+    th0 = ln.identity_theta()
+    l0 = ln.loss(op, th0, R, E)
+    th, hist = ln.train(op, th0, R, E, steps=40, L=4, lr=1e-2)
+    assert ln.loss(op, th, R, E) < 0.8 * l0
