@@ -74,7 +74,7 @@ typedef struct wd_ctx wd_ctx;
 /* preconditioner M of the solver */
 #define WD_PRECOND_NONE 0      /* M = I */
 #define WD_PRECOND_JACOBI 1    /* j-step Jacobi */
-#define WD_PRECOND_LEARNED 2   /* frozen linear gauge-covariant network (wd_set_learned) */
+#define WD_PRECOND_LEARNED 2   /* frozen linear gauge-covariant network (wd_set_learned), FP32 */
 
 /* reading of "diagonal part A_D" for the Jacobi preconditioner */
 #define WD_JACOBI_BLOCK 0      /* site-block diagonal: A_D = T(x) (12 x 12 per site) */
@@ -86,7 +86,8 @@ typedef struct wd_ctx wd_ctx;
 typedef struct wd_solve_opts {
     int j;                 /* Jacobi steps per application of M (>= 0); 0 means M = I */
     int precond;           /* WD_PRECOND_*; NONE forces j = 0 in the cost count */
-    int prec_inner;        /* WD_F64 / WD_F32 / WD_BF16 storage of the Jacobi preconditioner */
+    int prec_inner;        /* WD_F64 / WD_F32 / WD_BF16 storage of the Jacobi preconditioner
+                              (the learned preconditioner always runs in FP32) */
     int use_x0;            /* 1: X holds the initial guess; 0: start from X = 0 */
     int max_iter;          /* outer iterations per run; <= 0 means 5000 */
     int max_restarts;      /* true-residual restarts; < 0 means 3 */
@@ -94,6 +95,12 @@ typedef struct wd_solve_opts {
     double diverge_at;     /* <= 0 means 1e2 */
     double* history;       /* optional host buffer: max relative recursive residual per iteration */
     int history_len;       /* its length in doubles */
+    double cycle_tol;      /* Krylov cycle length for an inexact (low-precision) M: a cycle ends
+                              once it has reduced its starting residual by this factor, or when it
+                              stops improving (then X returns to the cycle's best iterate), and the
+                              solver restarts from the FP64 true residual.  0: 1e-4 for FP32 and
+                              1e-1 for BF16 storage of M (the learned M counts as FP32), no cycles
+                              for FP64; < 0: no cycles */
 } wd_solve_opts;
 
 /* Results of bbicggr_solve. */
@@ -102,6 +109,7 @@ typedef struct wd_solve_info {
     int iterations;                    /* outer iterations of the last run */
     int total_iterations;              /* over all restarts */
     int restarts;                      /* true-residual restarts made */
+    int cycles;                        /* Krylov cycles run (1 without low-precision cycling) */
     long long mvm_paper;               /* per column, counted as in Table 1: 2(j+1)k + 1 per run */
     long long mvm_actual;              /* per column: hopping-term applications actually made */
     double seconds;                    /* wall time of the solve (device synchronised) */
@@ -193,6 +201,53 @@ int wd_block_gram(wd_ctx* ctx, const void* P, const void* Q, int L, void* C);
  * Sec. 2).  Returns WD_BREAKDOWN if a pivot is below 1e-14 max|M| or M is
  * not finite. */
 int wd_small_solve(wd_ctx* ctx, const void* M, const void* RHS, int L, void* Z);
+
+/* ---------------------------------------------------------------------------
+ * Learned preconditioner (linear, gauge covariant, frozen after training)
+ * ------------------------------------------------------------------------- */
+
+/* Number of layers and weights: theta is complex64 [layer][d][4][4] with
+ * d = 0 the site term and d = 1 + 2 mu (+mu) / 2 + 2 mu (-mu) the hops.  A
+ * layer maps psi to W_0 psi(x) + sum_mu [W_{+mu} U_mu(x) psi(x+mu)
+ * + W_{-mu} U_mu(x-mu)^dag psi(x-mu)], W acting on spin; M_theta is the
+ * product of the layers (layer 0 applied first). */
+#define WD_LEARNED_LAYERS 3
+#define WD_LEARNED_DIRS 9
+
+/* Set theta (host pointer, 3*9*16 complex64 = interleaved float re, im). */
+int wd_set_learned(wd_ctx* ctx, const float* theta_host);
+
+/* Starting points for theta.  IDENTITY: W_0 = 1 and all hops 0 in every
+ * layer, so M_theta = 1.  NEUMANN: the truncated Neumann series
+ * 1 + x + x^2 + x^3 of (1 - x)^-1, x = kappa H (H the Wilson hopping term of
+ * the operator, Sec. 2), written as the product (1 + x)(1 + i x)(1 - i x):
+ * layer l has W_0 = 1, W_{+mu} = c_l kappa (1 - gamma_mu), W_{-mu} =
+ * c_l kappa (1 + gamma_mu), c = (1, i, -i).  NEUMANN needs wd_set_params
+ * (kappa) and ignores the clover term. */
+#define WD_LEARNED_INIT_IDENTITY 0
+#define WD_LEARNED_INIT_NEUMANN 1
+int wd_learned_init(wd_ctx* ctx, int kind);
+
+/* Z = M_theta R (FP64 in and out, FP32 arithmetic and storage inside); R and
+ * Z are device block vectors of L columns and must not overlap. */
+int wd_learned_apply(wd_ctx* ctx, const void* R, void* Z, int L);
+
+/* Train theta on pairs (r, e) with A e ~ r: minimise the mean over columns of
+ * ||M_theta r - e||^2 / ||e||^2 with Adam (lr, beta1 0.9, beta2 0.999) for
+ * `steps` steps; batch b uses columns [b*L, b*L + L) of the n_pairs columns
+ * of Rp and Ep (device block vectors of n_pairs columns each, FP64), cycling.
+ * Starts from the current theta and leaves the trained theta set.  loss_hist
+ * (host, may be NULL) receives one loss per step. */
+int wd_learned_train(wd_ctx* ctx, const void* Rp, const void* Ep, int n_pairs, int L,
+                     int steps, double lr, float* loss_hist);
+
+/* Copy the current theta to host memory (3*9*16 complex64). */
+int wd_get_learned(wd_ctx* ctx, float* theta_host);
+
+/* Loss (as in wd_learned_train) and its gradient with respect to theta on L
+ * pairs, without updating theta: G_host receives 3*9*16 complex128 holding
+ * dl/dRe(theta) + i dl/dIm(theta).  For testing the backward kernels. */
+int wd_learned_grad(wd_ctx* ctx, const void* R, const void* E, int L, double* loss, double* G_host);
 
 /* ---------------------------------------------------------------------------
  * Utilities

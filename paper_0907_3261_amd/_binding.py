@@ -34,6 +34,7 @@ WD_STAGNATED = 4
 
 WD_F64, WD_F32, WD_BF16 = 0, 1, 2
 WD_PRECOND_NONE, WD_PRECOND_JACOBI, WD_PRECOND_LEARNED = 0, 1, 2
+WD_LEARNED_INIT_IDENTITY, WD_LEARNED_INIT_NEUMANN = 0, 1
 WD_JACOBI_BLOCK, WD_JACOBI_POINT = 0, 1
 WD_MAX_L = 16
 
@@ -45,11 +46,13 @@ STATUS_NAME = {WD_OK: "converged", WD_NOT_CONVERGED: "not_converged", WD_BREAKDO
 class SolveOpts(ctypes.Structure):
     _fields_ = [("j", c_int), ("precond", c_int), ("prec_inner", c_int), ("use_x0", c_int),
                 ("max_iter", c_int), ("max_restarts", c_int), ("stagnate_window", c_int),
-                ("diverge_at", c_double), ("history", POINTER(c_double)), ("history_len", c_int)]
+                ("diverge_at", c_double), ("history", POINTER(c_double)), ("history_len", c_int),
+                ("cycle_tol", c_double)]
 
 
 class SolveInfo(ctypes.Structure):
     _fields_ = [("status", c_int), ("iterations", c_int), ("total_iterations", c_int), ("restarts", c_int),
+                ("cycles", c_int),
                 ("mvm_paper", c_longlong), ("mvm_actual", c_longlong), ("seconds", c_double),
                 ("bytes_alg", c_double),
                 ("true_residual", c_double * WD_MAX_L), ("recursive_residual", c_double * WD_MAX_L)]
@@ -75,6 +78,12 @@ SIGNATURES = [
     ("wd_hop_repeat", c_int, [c_void_p, c_void_p, c_void_p, c_void_p, c_int, c_int, c_int, c_int]),
     ("wd_block_gram", c_int, [c_void_p, c_void_p, c_void_p, c_int, c_void_p]),
     ("wd_small_solve", c_int, [c_void_p, c_void_p, c_void_p, c_int, c_void_p]),
+    ("wd_set_learned", c_int, [c_void_p, c_void_p]),
+    ("wd_learned_init", c_int, [c_void_p, c_int]),
+    ("wd_get_learned", c_int, [c_void_p, c_void_p]),
+    ("wd_learned_apply", c_int, [c_void_p, c_void_p, c_void_p, c_int]),
+    ("wd_learned_train", c_int, [c_void_p, c_void_p, c_void_p, c_int, c_int, c_int, c_double, c_void_p]),
+    ("wd_learned_grad", c_int, [c_void_p, c_void_p, c_void_p, c_int, c_void_p, c_void_p]),
     ("wd_strerror", ctypes.c_char_p, [c_int]),
     ("wd_volume", c_longlong, [c_void_p]),
 ]
@@ -207,7 +216,7 @@ class Context:
 
     def solve(self, B, X=None, tol: float = 1e-12, j: int = 0, precond: int | None = None,
               prec_inner: str = "f64", max_iter: int = 0, max_restarts: int = -1, diverge_at: float = 0.0,
-              stagnate_window: int = 0, history_len: int = 0):
+              stagnate_window: int = 0, history_len: int = 0, cycle_tol: float = 0.0):
         """Preconditioned block BiCGGR; returns (X, info dict).  X, if given, is the initial guess."""
         L = B.shape[0]
         use_x0 = X is not None
@@ -220,17 +229,18 @@ class Context:
                       max_iter=int(max_iter), max_restarts=int(max_restarts),
                       stagnate_window=int(stagnate_window), diverge_at=float(diverge_at),
                       history=ctypes.cast(hist, POINTER(c_double)) if history_len else None,
-                      history_len=int(history_len))
+                      history_len=int(history_len), cycle_tol=float(cycle_tol))
         info = SolveInfo()
         code = _check(self._lib.bbicggr_solve(self._h, self._block(B), self._block(X, L), L, float(tol),
                                               ctypes.byref(o), ctypes.byref(info)), "bbicggr_solve")
         d = dict(code=code, status=STATUS_NAME.get(code, str(code)), iterations=info.iterations,
-                 total_iterations=info.total_iterations, restarts=info.restarts, mvm_paper=info.mvm_paper,
+                 total_iterations=info.total_iterations, restarts=info.restarts, cycles=info.cycles,
+                 mvm_paper=info.mvm_paper,
                  mvm_actual=info.mvm_actual, seconds=info.seconds, bytes_alg=info.bytes_alg,
                  true_residual=np.array(info.true_residual[:L]),
                  recursive_residual=np.array(info.recursive_residual[:L]))
         if history_len:
-            d["history"] = np.array(hist[:min(history_len, info.total_iterations + 1 + info.restarts)])
+            d["history"] = np.array(hist[:min(history_len, info.total_iterations + info.cycles + info.restarts)])
         return X, d
 
     def hop_repeat(self, X, Y, nrep: int, mode: int = 0, R=None):
@@ -240,6 +250,45 @@ class Context:
         _check(self._lib.wd_hop_repeat(self._h, self._block(X), r, self._block(Y, L), L, int(mode), WD_F64,
                                        int(nrep)), "wd_hop_repeat")
         return Y
+
+    # ---- learned preconditioner
+    def set_learned(self, theta: np.ndarray):
+        """theta: complex array (3, 9, 4, 4), stored as complex64."""
+        a = np.ascontiguousarray(np.asarray(theta).reshape(3, 9, 4, 4), dtype=np.complex64)
+        _check(self._lib.wd_set_learned(self._h, a.ctypes.data), "wd_set_learned")
+
+    def learned_init(self, kind: str = "neumann"):
+        """theta := identity (M = 1) or the factored degree-3 Neumann series of (1 - kappa H)^-1."""
+        k = {"identity": WD_LEARNED_INIT_IDENTITY, "neumann": WD_LEARNED_INIT_NEUMANN}[kind]
+        _check(self._lib.wd_learned_init(self._h, k), "wd_learned_init")
+
+    def get_learned(self) -> np.ndarray:
+        a = np.empty((3, 9, 4, 4), dtype=np.complex64)
+        _check(self._lib.wd_get_learned(self._h, a.ctypes.data), "wd_get_learned")
+        return a
+
+    def learned_apply(self, R, Z=None):
+        L = R.shape[0]
+        if Z is None:
+            Z = self.empty_block(L)
+        _check(self._lib.wd_learned_apply(self._h, self._block(R), self._block(Z, L), L), "wd_learned_apply")
+        return Z
+
+    def learned_train(self, Rp, Ep, L: int, steps: int, lr: float = 1e-3):
+        """Train on pairs (Rp, Ep: device tensors of shape (P, 12, V)); returns the loss per step."""
+        P = Rp.shape[0]
+        hist = np.zeros(max(steps, 1), dtype=np.float32)
+        _check(self._lib.wd_learned_train(self._h, self._block(Rp), self._block(Ep, P), P, int(L), int(steps),
+                                          float(lr), hist.ctypes.data), "wd_learned_train")
+        return hist[:steps]
+
+    def learned_grad(self, R, E):
+        L = R.shape[0]
+        loss = ctypes.c_double()
+        G = np.empty((3, 9, 4, 4), dtype=np.complex128)
+        _check(self._lib.wd_learned_grad(self._h, self._block(R), self._block(E, L), L, ctypes.byref(loss),
+                                         G.ctypes.data), "wd_learned_grad")
+        return loss.value, G
 
     # ---- block kernels
     def gram(self, P, Q):

@@ -129,6 +129,8 @@ int wd_destroy(wd_ctx* c) {
     dev_free((void*&)c->partial);
     dev_free((void*&)c->small);
     dev_free((void*&)c->theta);
+    dev_free((void*&)c->U32);
+    dev_free(c->learn_mem);
     if (c->host_ctl) (void)hipHostFree(c->host_ctl);
     delete c;
     return WD_OK;
@@ -169,6 +171,8 @@ int wd_create(wd_ctx** out, const int dims[4], int bc_t, int max_L, void* hip_st
     for (auto& w : c->ws) r = r ? r : dev_alloc((void**)&w, block_elems(c, max_L) * 16);
     r = r ? r : dev_alloc((void**)&c->partial, (size_t)512 * partial_stride() * 16);
     r = r ? r : dev_alloc((void**)&c->small, kSmallPairs * 16);
+    r = r ? r : dev_alloc((void**)&c->U32, links * 8);
+    r = r ? r : dev_alloc((void**)&c->theta, (size_t)WD_LEARNED_LAYERS * WD_LEARNED_DIRS * 16 * 8);
     if (!r && hipHostMalloc((void**)&c->host_ctl, sizeof(Ctl)) != hipSuccess) r = WD_ENOMEM;
     if (r) {
         wd_destroy(c);
@@ -199,6 +203,7 @@ int wd_set_links(wd_ctx* c, const double* U, int on_device) {
         src = (const double2*)staging;
     }
     hipError_t e = launch_links_from_abi(src, c->f.U, c->g, c->bc_t, c->stream);
+    if (e == hipSuccess) e = launch_convert(c->f.U, c->U32, Prec::F32, 1.0, n, c->stream);
     if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
     if (staging && staging != c->ws[WS_T2]) dev_free(staging);
     if (e != hipSuccess) return WD_EHIP;
@@ -353,6 +358,13 @@ struct Solver {
     void blocks(double n) { bytes += n * 192.0 * L * c->g.V; }
 
     int applyM(const double2* in, double2* out) {
+        if (precond == WD_PRECOND_LEARNED) {
+            WD_TRY_HIP(launch_learned(c, in, out, L, c->stream));
+            mvm_actual += WD_LEARNED_LAYERS;
+            // three FP32 layers: links 288 B per site each, FP64 in (first) and out (last)
+            bytes += (double)c->g.V * (3 * 288.0 + 192.0 * L + 4 * 96.0 * L + 192.0 * L);
+            return WD_OK;
+        }
         if (precond == WD_PRECOND_JACOBI && j > 0) {
             WD_TRY_HIP(launch_jacobi(c, in, out, L, j, pin, c->stream));
             mvm_actual += j - 1;
@@ -393,9 +405,15 @@ int bbicggr_solve(wd_ctx* c, const void* Bv, void* Xv, int L, double tol, const 
     if (!c->have_params) return WD_ESTATE;
     wd_solve_opts op{};
     if (o) op = *o;
-    if (op.precond != WD_PRECOND_NONE && op.precond != WD_PRECOND_JACOBI) return WD_EINVAL;
+    if (op.precond != WD_PRECOND_NONE && op.precond != WD_PRECOND_JACOBI && op.precond != WD_PRECOND_LEARNED)
+        return WD_EINVAL;
     if (op.j < 0 || check_prec(op.prec_inner)) return WD_EINVAL;
-    if (op.precond == WD_PRECOND_NONE) op.j = 0;
+    if (op.precond == WD_PRECOND_LEARNED) {
+        if (!c->have_theta) return WD_ESTATE;
+        int r0 = learned_ensure(c);
+        if (r0) return r0;
+    }
+    if (op.precond != WD_PRECOND_JACOBI) op.j = 0;
     const int max_iter = op.max_iter > 0 ? op.max_iter : 5000;
     const int max_restarts = op.max_restarts >= 0 ? op.max_restarts : 3;
     const int stag = op.stagnate_window > 0 ? op.stagnate_window : 200;
@@ -439,9 +457,19 @@ int bbicggr_solve(wd_ctx* c, const void* Bv, void* Xv, int L, double tol, const 
 
     Ctl* hc = reinterpret_cast<Ctl*>(c->host_ctl);
     int status = WD_NOT_CONVERGED;
-    int iters = 0, total_iters = 0, restarts = 0, hist_pos = 0;
+    int iters = 0, total_iters = 0, restarts = 0, cycles = 0, hist_pos = 0;
     bool use_x0 = op.use_x0 != 0;
     double true_rel[WD_MAX_L] = {0}, rec_rel[WD_MAX_L] = {0};
+    // Krylov cycles for an inexact M (low-precision storage of the Jacobi preconditioner)
+    const bool learned_M = op.precond == WD_PRECOND_LEARNED;
+    const bool inexact_M = learned_M || (op.precond == WD_PRECOND_JACOBI && op.j > 0 && op.prec_inner != WD_F64);
+    double cycle_tol = op.cycle_tol;
+    if (cycle_tol == 0.0) cycle_tol = inexact_M ? ((learned_M || op.prec_inner == WD_F32) ? 1e-4 : 1e-1) : -1.0;
+    const bool cycling = cycle_tol > 0.0;
+    const int cycle_stag = 20;   // iterations without improvement that end a cycle
+    const int max_cycles = 200;
+    double2* Xbest = S.ws(WS_T2);
+    constexpr int kCycleEnd = 100;  // internal run status: restart from X
 
     auto record = [&](double v) {
         if (op.history && hist_pos < op.history_len) op.history[hist_pos] = v;
@@ -449,6 +477,7 @@ int bbicggr_solve(wd_ctx* c, const void* Bv, void* Xv, int L, double tol, const 
     };
 
     for (;;) {
+        ++cycles;
         // ---- initialisation: R0 = B - A X0, P0 = R0, Rt0 = R0, F0 = M R0, V0 = W0 = A F0
         if (use_x0) {
             if ((r = S.applyA(X, T1))) return r;
@@ -479,8 +508,10 @@ int bbicggr_solve(wd_ctx* c, const void* Bv, void* Xv, int L, double tol, const 
         record(res);
         iters = 0;
         int run_status = WD_NOT_CONVERGED;
+        const double res0 = res;
         double best = res;
         int best_k = 0;
+        bool have_best = false;  // Xbest holds an iterate better than the cycle's start
         if (res <= tol) run_status = WD_OK;
         for (int k = 0; run_status == WD_NOT_CONVERGED && k < max_iter; ++k) {
             // alpha and zeta
@@ -488,7 +519,7 @@ int bbicggr_solve(wd_ctx* c, const void* Bv, void* Xv, int L, double tol, const 
             WD_TRY_HIP(launch_solve_alpha(c->partial, S.nb, L, S.bufs, st));
             // U = (P - zeta V) alpha ; G = M U ; Y = A G
             WD_TRY_HIP(launch_update_U(P, V, S.sl.zeta, S.sl.alpha, U, N, L, st));
-            S.blocks(4 + 3 + 9);
+            S.blocks(4 + 3 + 11);
             const long long mp = S.mvm_paper, ma = S.mvm_actual;
             if ((r = S.applyM(U, G))) return r;
             if ((r = S.applyA(G, Y))) return r;
@@ -519,6 +550,11 @@ int bbicggr_solve(wd_ctx* c, const void* Bv, void* Xv, int L, double tol, const 
                 run_status = WD_OK;
                 break;
             }
+            if (cycling && res <= cycle_tol * res0) {
+                run_status = kCycleEnd;
+                break;
+            }
+            const int window = cycling ? cycle_stag : stag;
             if (res > diverge_at) {
                 run_status = WD_DIVERGED;
                 break;
@@ -526,7 +562,12 @@ int bbicggr_solve(wd_ctx* c, const void* Bv, void* Xv, int L, double tol, const 
             if (res < best) {
                 best = res;
                 best_k = k + 1;
-            } else if (k + 1 - best_k >= stag) {
+                if (cycling) {
+                    WD_TRY_HIP(launch_copy(Xbest, X, N * L, st));
+                    S.blocks(2);
+                    have_best = true;
+                }
+            } else if (k + 1 - best_k >= window) {
                 run_status = WD_STAGNATED;
                 break;
             }
@@ -542,6 +583,19 @@ int bbicggr_solve(wd_ctx* c, const void* Bv, void* Xv, int L, double tol, const 
             S.blocks(6);
         }
         total_iters += iters;
+        // an inexact M: a cycle that stalled or blew up restarts from its best iterate, if it has one
+        if (cycling && cycles < max_cycles &&
+            (run_status == WD_STAGNATED || run_status == WD_DIVERGED || run_status == WD_BREAKDOWN ||
+             run_status == WD_NOT_CONVERGED) && have_best && best < res0) {
+            WD_TRY_HIP(launch_copy(X, Xbest, N * L, st));
+            S.blocks(2);
+            run_status = kCycleEnd;
+        }
+        if (run_status == kCycleEnd && cycles < max_cycles) {
+            use_x0 = true;
+            continue;
+        }
+        if (run_status == kCycleEnd) run_status = WD_NOT_CONVERGED;
         status = run_status;
         if (status == WD_ENAN) break;
         // ---- true residual ||B - A X|| / ||B|| in FP64
@@ -573,6 +627,7 @@ int bbicggr_solve(wd_ctx* c, const void* Bv, void* Xv, int L, double tol, const 
         info->iterations = iters;
         info->total_iterations = total_iters;
         info->restarts = restarts;
+        info->cycles = cycles;
         info->mvm_paper = S.mvm_paper;
         info->mvm_actual = S.mvm_actual;
         info->seconds = secs;

@@ -172,52 +172,6 @@ __global__ void __launch_bounds__(kWG) k_gram1(const double2* __restrict__ Rt, c
     }
 }
 
-// ---- X += zeta F + G ; Rn = R - zeta W - Y ; tile Rt^H Rn ; extras = ||Rn_i||^2
-__global__ void __launch_bounds__(kWG) k_update_XR(double2* __restrict__ X, double2* __restrict__ R,
-                                                   const double2* __restrict__ F, const double2* __restrict__ G,
-                                                   const double2* __restrict__ W, const double2* __restrict__ Y,
-                                                   const double2* __restrict__ Rt, const double2* __restrict__ zp,
-                                                   size_t N, int L, double2* __restrict__ partial, int nb) {
-    __shared__ double2 sh[kWG / 64 * 256];
-    const RowRange rr = block_rows(N, nb);
-    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-    const int col = lane & 15, q = lane >> 4;
-    const bool colok = col < L;
-    const cx<double> z = StF64::ld(zp, 0);
-    GramAcc acc;
-    gram_zero(acc);
-    double nrm = 0.0;
-    for (size_t n0 = rr.r0 + 16 * w; n0 < rr.r1; n0 += 16 * (kWG / 64)) {
-        cx<double> a[4], b[4];
-#pragma unroll
-        for (int r = 0; r < 4; ++r) {
-            const size_t n = n0 + 4 * r + q;
-            const bool ok = colok && n < rr.r1;
-            a[r] = {0.0, 0.0};
-            b[r] = {0.0, 0.0};
-            if (ok) {
-                const size_t idx = (size_t)col * N + n;
-                cx<double> x = StF64::ld(X, idx);
-                cfma(x, z, StF64::ld(F, idx));
-                x = x + StF64::ld(G, idx);
-                StF64::st(X, idx, x);
-                cx<double> rn = StF64::ld(R, idx) - StF64::ld(Y, idx);
-                cfma(rn, -z, StF64::ld(W, idx));
-                StF64::st(R, idx, rn);
-                a[r] = StF64::ld(Rt, idx);
-                b[r] = rn;
-                nrm += rn.re * rn.re + rn.im * rn.im;
-            }
-        }
-#pragma unroll
-        for (int r = 0; r < 4; ++r) gram_step(acc, a[r], b[r]);
-    }
-    double2* out = partial + (size_t)blockIdx.x * kPStride;
-    gram_store(acc, out, sh);
-    __syncthreads();
-    colsum_store(nrm, out, reinterpret_cast<double*>(sh));
-}
-
 // ---- column norms only (extras)
 __global__ void __launch_bounds__(kWG) k_colnorms(const double2* __restrict__ R, size_t N, int L,
                                                   double2* __restrict__ partial, int nb) {
@@ -495,6 +449,49 @@ __global__ void __launch_bounds__(kWG) k_update_U(const double2* __restrict__ P,
     }
 }
 
+// X += zeta F + G ; R <- R - zeta W - Y ; per-column ||R||^2 into the partial
+// extras (one thread per row, L columns; coalesced across the wavefront).
+template <int L>
+__global__ void __launch_bounds__(kWG) k_update_XR_rows(double2* __restrict__ X, double2* __restrict__ R,
+                                                        const double2* __restrict__ F, const double2* __restrict__ G,
+                                                        const double2* __restrict__ W, const double2* __restrict__ Y,
+                                                        const double2* __restrict__ zp, size_t N,
+                                                        double2* __restrict__ partial, int nb) {
+    __shared__ double shd[kWG / 64 * 16];
+    const RowRange rr = block_rows(N, nb);
+    const cx<double> z = StF64::ld(zp, 0);
+    double nrm[L];
+#pragma unroll
+    for (int i = 0; i < L; ++i) nrm[i] = 0.0;
+    for (size_t n = rr.r0 + threadIdx.x; n < rr.r1; n += kWG) {
+#pragma unroll
+        for (int i = 0; i < L; ++i) {
+            const size_t idx = (size_t)i * N + n;
+            cx<double> x = StF64::ld(X, idx);
+            cfma(x, z, StF64::ld(F, idx));
+            x = x + StF64::ld(G, idx);
+            StF64::st(X, idx, x);
+            cx<double> rn = StF64::ld(R, idx) - StF64::ld(Y, idx);
+            cfma(rn, -z, StF64::ld(W, idx));
+            StF64::st(R, idx, rn);
+            nrm[i] += rn.re * rn.re + rn.im * rn.im;
+        }
+    }
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+#pragma unroll
+    for (int i = 0; i < L; ++i) {
+        const double v = wave_sum(nrm[i]);
+        if (lane == 0) shd[w * 16 + i] = v;
+    }
+    __syncthreads();
+    if (threadIdx.x < 16) {
+        double sum = 0.0;
+        if ((int)threadIdx.x < L)
+            for (int q = 0; q < kWG / 64; ++q) sum += shd[q * 16 + threadIdx.x];
+        partial[(size_t)blockIdx.x * kPStride + 256 + threadIdx.x] = make_double2(sum, 0.0);
+    }
+}
+
 template <int L>
 __global__ void __launch_bounds__(kWG) k_update_PV(double2* __restrict__ P, double2* __restrict__ V,
                                                    const double2* __restrict__ R, const double2* __restrict__ W,
@@ -586,13 +583,6 @@ hipError_t launch_solve_gamma(const double2* partial, int nb, int L, const Solve
     return hipGetLastError();
 }
 
-hipError_t launch_update_XR(double2* X, double2* R, const double2* F, const double2* G, const double2* W,
-                            const double2* Y, const double2* Rt, const double2* zeta, size_t N, int L,
-                            double2* partial, int nb, hipStream_t s) {
-    k_update_XR<<<nb, kWG, 0, s>>>(X, R, F, G, W, Y, Rt, zeta, N, L, partial, nb);
-    return hipGetLastError();
-}
-
 #define WD_L_SWITCH(L, CALL)          \
     switch (L) {                      \
         case 1: CALL(1); break;       \
@@ -627,6 +617,19 @@ hipError_t launch_update_PV(double2* P, double2* V, const double2* R, const doub
 #define WD_CALL_PV(l) k_update_PV<l><<<nblk(N, kWG), kWG, 0, s>>>(P, V, R, W, U, Y, gamma, N)
     WD_L_SWITCH(L, WD_CALL_PV)
 #undef WD_CALL_PV
+    return hipGetLastError();
+}
+
+hipError_t launch_update_XR(double2* X, double2* R, const double2* F, const double2* G, const double2* W,
+                            const double2* Y, const double2* Rt, const double2* zeta, size_t N, int L,
+                            double2* partial, int nb, hipStream_t s) {
+    // the update writes the norm extras, the Gram kernel the tile of the same partial blocks
+#define WD_CALL_XR(l) k_update_XR_rows<l><<<nb, kWG, 0, s>>>(X, R, F, G, W, Y, zeta, N, partial, nb)
+    WD_L_SWITCH(L, WD_CALL_XR)
+#undef WD_CALL_XR
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    k_gram<<<nb, kWG, 0, s>>>(Rt, R, N, L, partial, nb);
     return hipGetLastError();
 }
 

@@ -183,6 +183,7 @@ __global__ void __launch_bounds__(256)
     const int t = s / g.sxyz;
     const uint32_t PB = sizeof(PF);
     const uint32_t o_s = (uint32_t)s * PB;
+    const uint32_t o_y = (uint32_t)s * (uint32_t)sizeof(PY);  // the output may have another pair size
     const uint32_t o_fx = (uint32_t)((x == g.lx - 1) ? s - (g.lx - 1) : s + 1) * PB;
     const uint32_t o_bx = (uint32_t)((x == 0) ? s + (g.lx - 1) : s - 1) * PB;
     const uint32_t o_fy = (uint32_t)((y == g.ly - 1) ? s - (g.ly - 1) * g.lx : s + g.lx) * PB;
@@ -240,7 +241,7 @@ __global__ void __launch_bounds__(256)
 #pragma unroll
         for (int c = 0; c < CT; ++c)
 #pragma unroll
-            for (int k = 0; k < 12; ++k) store_out<SY>(Yc + (size_t)c * cs + (size_t)k * V, o_s, acc[c][k]);
+            for (int k = 0; k < 12; ++k) store_out<SY>(Yc + (size_t)c * cs + (size_t)k * V, o_y, acc[c][k]);
     } else {
 #pragma unroll
         for (int chir = 0; chir < 2; ++chir) {
@@ -270,7 +271,7 @@ __global__ void __launch_bounds__(256)
                                 if (j != i) q = q - T.at(i, j) * xs[j];
                             r = T.d[i] * q;
                         }
-                        store_out<SY>(Yc + (size_t)c * cs + (size_t)(6 * chir + i) * V, o_s, r);
+                        store_out<SY>(Yc + (size_t)c * cs + (size_t)(6 * chir + i) * V, o_y, r);
                     }
                 }
             }
@@ -286,42 +287,43 @@ template <class SI, class SF, class SY, int MODE>
 __global__ void __launch_bounds__(256)
     k_first_sweep(const Geom g, const typename SF::P* __restrict__ Cl, const typename SI::P* __restrict__ Rin,
                   typename SF::P* __restrict__ RL, typename SY::P* __restrict__ Y, const int L) {
+    // one thread per site; the site's A_D^{-1} block stays in registers for all L columns
     using R = typename SF::R;
     const size_t V = g.V;
-    const int sblocks = (g.V + 255) / 256;
-    const int col = blockIdx.x / sblocks;
-    const int s = (blockIdx.x % sblocks) * 256 + threadIdx.x;
-    if (s >= g.V || col >= L) return;
+    const int s = blockIdx.x * 256 + threadIdx.x;
+    if (s >= g.V) return;
     const size_t cs = 12 * V;
     const uint32_t oF = (uint32_t)s * sizeof(typename SF::P);
     const uint32_t oI = (uint32_t)s * sizeof(typename SI::P);
     const uint32_t oY = (uint32_t)s * sizeof(typename SY::P);
-    const typename SI::P* Rc = Rin + (size_t)col * cs;
 #pragma unroll
     for (int chir = 0; chir < 2; ++chir) {
         Herm6<SF> T;
         T.load(Cl, chir, oF, V);
-        cx<R> v[6];
+        for (int col = 0; col < L; ++col) {
+            const typename SI::P* Rc = Rin + (size_t)col * cs;
+            cx<R> v[6];
 #pragma unroll
-        for (int k = 0; k < 6; ++k) {
-            const auto w = SI::ldb(Rc + (size_t)(6 * chir + k) * V, oI);
-            v[k] = {(R)w.re, (R)w.im};
-            if (RL != nullptr) {
-                // later sweeps read the rounded copy; use the same rounded value here
-                SF::stb(RL + (size_t)col * cs + (size_t)(6 * chir + k) * V, oF, v[k]);
-                v[k] = SF::rnd(v[k]);
+            for (int k = 0; k < 6; ++k) {
+                const auto w = SI::ldb_nt(Rc + (size_t)(6 * chir + k) * V, oI);
+                v[k] = {(R)w.re, (R)w.im};
+                if (RL != nullptr) {
+                    // later sweeps read the rounded copy; use the same rounded value here
+                    SF::stb(RL + (size_t)col * cs + (size_t)(6 * chir + k) * V, oF, v[k]);
+                    v[k] = SF::rnd(v[k]);
+                }
             }
-        }
 #pragma unroll
-        for (int r = 0; r < 6; ++r) {
-            cx<R> o = {R(0), R(0)};
-            if (MODE == JBLOCK) {
+            for (int r = 0; r < 6; ++r) {
+                cx<R> o = {R(0), R(0)};
+                if (MODE == JBLOCK) {
 #pragma unroll
-                for (int j = 0; j < 6; ++j) cfma(o, T.at(r, j), v[j]);
-            } else {
-                o = T.d[r] * v[r];
+                    for (int j = 0; j < 6; ++j) cfma(o, T.at(r, j), v[j]);
+                } else {
+                    o = T.d[r] * v[r];
+                }
+                store_out<SY>(Y + (size_t)col * cs + (size_t)(6 * chir + r) * V, oY, o);
             }
-            store_out<SY>(Y + (size_t)col * cs + (size_t)(6 * chir + r) * V, oY, o);
         }
     }
 }
@@ -391,7 +393,7 @@ hipError_t launch_hop_t(const Geom& g, const void* Uk, const void* Cl, const voi
 
 template <class SI, class SF, class SY>
 hipError_t launch_first(const wd_ctx* c, const void* Cl, const void* Rin, void* RL, void* Y, int L, hipStream_t s) {
-    const unsigned nb = (unsigned)((c->g.V + 255) / 256) * L;
+    const unsigned nb = (unsigned)((c->g.V + 255) / 256);
     if (c->jacobi_kind == WD_JACOBI_POINT)
         k_first_sweep<SI, SF, SY, JPOINT><<<nb, 256, 0, s>>>(c->g, (const typename SF::P*)Cl,
                                                               (const typename SI::P*)Rin, (typename SF::P*)RL,

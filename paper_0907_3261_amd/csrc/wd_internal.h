@@ -125,12 +125,12 @@ struct StF32 {
     WD_BYTE_OFFSET_ACCESSORS
 };
 
-// bfloat16 pair packed in 32 bits: low half = re, high half = im.
-__host__ __device__ __forceinline__ uint32_t f32_to_bf16_rne(float f) {
-    uint32_t u = __float_as_uint(f);
-    if ((u & 0x7f800000u) == 0x7f800000u && (u & 0x007fffffu)) return (u >> 16) | 0x40u;  // quiet NaN
-    u += 0x7fffu + ((u >> 16) & 1u);
-    return u >> 16;
+// bfloat16 pair packed in 32 bits: low half = re, high half = im.  The
+// conversion is the gfx950 packed convert (round to nearest even, NaN kept).
+typedef __bf16 wd_bf16x2 __attribute__((ext_vector_type(2)));
+__device__ __forceinline__ uint32_t pack_bf16(float re, float im) {
+    const wd_fvec2 f = {re, im};
+    return __builtin_bit_cast(uint32_t, __builtin_convertvector(f, wd_bf16x2));
 }
 struct StBF16 {
     using R = float;
@@ -140,19 +140,18 @@ struct StBF16 {
         const uint32_t v = __builtin_nontemporal_load(p);
         return {__uint_as_float(v << 16), __uint_as_float(v & 0xffff0000u)};
     }
-    __device__ __forceinline__ static void st_nt(P* p, cx<R> v) {
-        __builtin_nontemporal_store(f32_to_bf16_rne(v.re) | (f32_to_bf16_rne(v.im) << 16), p);
-    }
+    __device__ __forceinline__ static void st_nt(P* p, cx<R> v) { __builtin_nontemporal_store(pack_bf16(v.re, v.im), p); }
     __device__ __forceinline__ static cx<R> ld(const P* p, size_t i) {
         uint32_t v = p[i];
         return {__uint_as_float(v << 16), __uint_as_float(v & 0xffff0000u)};
     }
     __device__ __forceinline__ static void st(P* p, size_t i, cx<R> v) {
-        p[i] = f32_to_bf16_rne(v.re) | (f32_to_bf16_rne(v.im) << 16);
+        p[i] = pack_bf16(v.re, v.im);
     }
     // value after a round trip through the storage format
     __device__ __forceinline__ static cx<R> rnd(cx<R> v) {
-        return {__uint_as_float(f32_to_bf16_rne(v.re) << 16), __uint_as_float(f32_to_bf16_rne(v.im) << 16)};
+        const uint32_t b = pack_bf16(v.re, v.im);
+        return {__uint_as_float(b << 16), __uint_as_float(b & 0xffff0000u)};
     }
     WD_BYTE_OFFSET_ACCESSORS
 };
@@ -282,9 +281,12 @@ struct wd_ctx {
     double2* small = nullptr;     // L x L matrices, scalars (see wd_blas.hip)
     int* dstatus = nullptr;
     double* host_ctl = nullptr;   // pinned host mirror of per-iteration control data
-    // learned preconditioner
+    // learned preconditioner: FP32 links (unscaled), weights, training workspace
+    float2* U32 = nullptr;
     float2* theta = nullptr;
     bool have_theta = false;
+    void* learn_mem = nullptr;
+    size_t learn_bytes = 0;
 };
 
 namespace wd {
@@ -313,6 +315,10 @@ inline double bytes_sweep(int L) { return 1152.0 + 576.0 * L; }
 inline double bytes_first_sweep(int L) { return 576.0 + 384.0 * L; }
 // low precision application of A (diagnostic): Y (FP64) = A X computed in p
 hipError_t launch_apply_A_lowp(wd_ctx* c, const double2* X, double2* Y, int L, Prec p, hipStream_t s);
+
+// ---- learned preconditioner (wd_learned.hip): Z = M_theta R, FP64 in and out
+hipError_t launch_learned(wd_ctx* c, const double2* R, double2* Z, int L, hipStream_t s);
+int learned_ensure(wd_ctx* c);
 
 // ---- block kernels (wd_blas.hip)
 size_t partial_stride();  // complex entries per partial block

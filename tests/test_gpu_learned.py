@@ -1,0 +1,166 @@
+"""Learned linear preconditioner on the GPU (FP32) against the FP64 oracle.
+
+Bounds from the arithmetic: a layer output element sums 9 x 4 x (3 + 1)
+products of FP32-rounded inputs, links and weights, so after three layers
+the error relative to the largest output element stays below ~3 x 150 u32
+(u32 = 2^-24) times |terms| / |result| (~10 for random weights): 1e-4 is
+used for applications and for the gradient (a sum over V * 3 * L terms
+accumulated in FP64 from FP32 products, error ~ u32 relative).
+"""
+
+import sys
+
+import numpy as np
+import pytest
+
+import wdinputs as wi
+from oracle import WilsonClover, gammas
+from oracle import learned as ln
+from oracle.bbicggr import true_residual
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module")
+def pkg():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_0907_3261_amd as p
+    p.load()
+    return p
+
+
+def _say(msg):
+    sys.__stderr__.write(f"[learned] {msg}\n")
+    sys.__stderr__.flush()
+
+
+def _ctx(pkg, dims, kappa=0.12, csw=1.0, bc_t=1, max_L=12, seed=401):
+    U = wi.random_links(dims, 0.3, seed)
+    c = pkg.Context(dims, bc_t=bc_t, max_L=max_L)
+    c.set_links(U)
+    c.set_params(kappa, csw)
+    return c, WilsonClover(dims, U, kappa, csw, bc_t=bc_t)
+
+
+def _theta(seed, scale=0.25):
+    rng = np.random.default_rng(seed)
+    th = ln.identity_theta()
+    th += scale * (rng.standard_normal(th.shape) + 1j * rng.standard_normal(th.shape))
+    return th.astype(np.complex64).astype(np.complex128)
+
+
+def _maxrel(a, b):
+    return np.max(np.abs(a - b)) / np.max(np.abs(b))
+
+
+@pytest.mark.parametrize("dims,L", [((4, 4, 4, 6), 3), ((8, 6, 4, 4), 12), ((3, 5, 4, 2), 1)])
+def test_apply_matches_oracle(pkg, dims, L):
+    c, op = _ctx(pkg, dims)
+    th = _theta(1)
+    c.set_learned(th)
+    R = wi.gaussian_block(op.V, L, 402)
+    Z = c.learned_apply(torch.from_numpy(R).cuda()).cpu().numpy()
+    Zo = op.to_block(ln.forward(op, th, op.from_block(R)))
+    err = _maxrel(Z, Zo)
+    _say(f"apply {dims} L={L}: {err:.2e}")
+    assert err < 1e-4
+    assert np.allclose(c.get_learned(), th.astype(np.complex64))
+    c.close()
+
+
+def test_identity_and_wilson_reduction(pkg):
+    dims = (4, 4, 4, 4)
+    c, op = _ctx(pkg, dims, kappa=0.13, csw=0.0, bc_t=0)
+    R = wi.gaussian_block(op.V, 4, 403)
+    Rd = torch.from_numpy(R).cuda()
+    c.set_learned(ln.identity_theta())
+    assert _maxrel(c.learned_apply(Rd).cpu().numpy(), R) < 1e-7
+    th = ln.identity_theta()
+    g = gammas()
+    for mu in range(4):
+        th[0, 1 + 2 * mu] = 0.13 * (np.eye(4) - g[mu])
+        th[0, 2 + 2 * mu] = 0.13 * (np.eye(4) + g[mu])
+    c.set_learned(th)
+    Z = c.learned_apply(Rd).cpu().numpy()
+    AR = c.apply(Rd).cpu().numpy()
+    assert _maxrel(Z, 2 * R - AR) < 1e-6        # one layer = 1 + kappa H = 2 - A at c_SW = 0
+    c.close()
+
+
+@pytest.mark.parametrize("L", [1, 3])
+def test_gradient_matches_oracle(pkg, L):
+    dims = (4, 4, 2, 4)
+    c, op = _ctx(pkg, dims)
+    th = _theta(2, 0.2)
+    c.set_learned(th)
+    R = wi.gaussian_block(op.V, L, 404)
+    E = wi.gaussian_block(op.V, L, 405)
+    lv, G = c.learned_grad(torch.from_numpy(R).cuda(), torch.from_numpy(E).cuda())
+    lo, Go = ln.grad(op, th, op.from_block(R), op.from_block(E))
+    _say(f"grad L={L}: loss {lv:.6e} vs {lo:.6e}, G maxrel {_maxrel(G, Go):.2e}")
+    assert abs(lv - lo) / lo < 1e-5
+    assert _maxrel(G, Go) < 1e-4
+    c.close()
+
+
+def _neumann_theta(kappa):
+    """The factored series (1 + x)(1 + i x)(1 - i x), x = kappa H, built from the oracle's gammas."""
+    g = gammas()
+    th = np.zeros((3, 9, 4, 4), dtype=np.complex128)
+    for l, cf in enumerate((1.0, 1j, -1j)):
+        th[l, 0] = np.eye(4)
+        for mu in range(4):
+            th[l, 1 + 2 * mu] = cf * kappa * (np.eye(4) - g[mu])
+            th[l, 2 + 2 * mu] = cf * kappa * (np.eye(4) + g[mu])
+    return th
+
+
+def test_neumann_init_is_truncated_series(pkg):
+    dims = (4, 6, 4, 4)
+    kappa = 0.11
+    c, op = _ctx(pkg, dims, kappa=kappa, csw=0.0, bc_t=1)
+    c.learned_init("neumann")
+    assert np.allclose(c.get_learned(), _neumann_theta(kappa).astype(np.complex64), atol=1e-7)
+    R = wi.gaussian_block(op.V, 5, 409)
+    f = op.from_block(R)
+    want, term = f.copy(), f
+    for _ in range(3):
+        term = kappa * op.hop(term)
+        want = want + term
+    Z = c.learned_apply(torch.from_numpy(R).cuda()).cpu().numpy()
+    err = _maxrel(Z, op.to_block(want))
+    _say(f"neumann init vs 1 + x + x^2 + x^3: {err:.2e}")
+    assert err < 1e-5
+    c.learned_init("identity")
+    assert np.allclose(c.get_learned(), ln.identity_theta().astype(np.complex64))
+    c.close()
+
+
+def test_training_lowers_loss_and_solves(pkg):
+    """Train from the Neumann start on pairs (A e, e) with Gaussian e, then solve to 1e-12.
+
+    The learned M is applied in FP32, so the solve runs in Krylov cycles; its
+    true residual is checked with the oracle's operator."""
+    dims = (8, 8, 8, 8)
+    kappa = 0.12
+    c, op = _ctx(pkg, dims, kappa=kappa, csw=1.6, bc_t=0)
+    L = 4
+    B = torch.from_numpy(wi.gaussian_block(op.V, L, 406)).cuda()
+    Ep = torch.from_numpy(wi.gaussian_block(op.V, 24, 407)).cuda()
+    Rp = torch.cat([c.apply(Ep[i:i + L]) for i in range(0, 24, L)]).contiguous()
+    c.learned_init("neumann")
+    hist = c.learned_train(Rp, Ep, L, steps=40, lr=1e-3)
+    _say(f"train loss {hist[:4]} -> {hist[-4:]}")
+    assert np.all(np.isfinite(hist))
+    assert hist[-6:].mean() < hist[:6].mean()
+    X, info = c.solve(B, tol=1e-12, precond=pkg.WD_PRECOND_LEARNED)
+    assert info["status"] == "converged", info
+    tr = true_residual(op.A_mat, op.block_to_mat(B.cpu().numpy()), op.block_to_mat(X.cpu().numpy()))
+    assert np.max(tr) <= 1e-12
+    X0, i0 = c.solve(B, tol=1e-12, j=0)
+    assert i0["status"] == "converged"
+    _say(f"iterations: learned M {info['total_iterations']} (cycles {info['cycles']}), M = 1 {i0['iterations']}")
+    assert info["total_iterations"] < i0["iterations"]
+    c.close()

@@ -1,0 +1,121 @@
+"""Low-precision (FP32 / BF16 storage, FP32 arithmetic) operator and Jacobi
+preconditioner against the FP64 oracle, and mixed-precision solves that must
+still reach the FP64 true residual.
+
+Error bounds derived from the arithmetic (u = unit roundoff of the storage
+format: 2^-24 for FP32, 2^-8 for BF16 with round-to-nearest-even):
+
+* one application of A: every output element is a sum of about 100 products
+  of rounded inputs (8 hops x 2 spin components x 3 colours, plus the 6 x 6
+  clover row), each product carrying the rounding of two stored factors
+  (2u) and the FP32 accumulation adding at most ~100 u32; with
+  sum |terms| / |result| ~ 3 on these fields the error relative to the
+  largest output element stays below 1e3 u32 = 6e-5 for FP32 storage, and
+  below 9 u = 3.5e-2 for BF16 storage (2u per product times the factor 3,
+  with margin; the FP32 accumulation is negligible there).
+* j Jacobi sweeps: each sweep adds the one-application error and the
+  iteration matrix (spectral radius ~1 here) carries earlier errors along,
+  so the bound grows linearly in j.
+* solves: X and R are updated in FP64 from F = M R and G = M U, and W = A F,
+  Y = A G are formed in FP64 (Sec. 2, algorithm box), so any M -- however
+  inexact -- only changes the iteration count: the true residual must still
+  reach 1e-12.
+"""
+
+import json
+import os
+import sys
+
+import numpy as np
+import pytest
+
+import wdinputs as wi
+from oracle import WilsonClover
+from oracle.jacobi import jacobi_apply
+from oracle.bbicggr import true_residual
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+U32 = 2.0 ** -24
+UBF = 2.0 ** -8
+APPLY_TOL = {"f32": 1e3 * U32, "bf16": 9 * UBF}
+SWEEP_TOL = {"f32": 1e3 * U32, "bf16": 9 * UBF}
+RESULTS = {}
+
+
+def _record(key, val):
+    RESULTS[key] = float(val)
+    sys.__stderr__.write(f"[lowp] {key} = {val:.3e}\n")
+    out = os.path.join(os.environ.get("GRAFT_REPO_ROOT", "."), "gpurun_out")
+    if os.path.isdir(out):
+        with open(os.path.join(out, "lowp_errors.json"), "w") as f:
+            json.dump(RESULTS, f, indent=1)
+
+
+@pytest.fixture(scope="module")
+def pkg():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_0907_3261_amd as p
+    p.load()
+    return p
+
+
+def _setup(pkg, dims=(8, 8, 8, 8), kappa=0.127, csw=1.6, bc_t=1, eps=0.3, max_L=12):
+    U = wi.random_links(dims, eps, 301)
+    c = pkg.Context(dims, bc_t=bc_t, max_L=max_L)
+    c.set_links(U)
+    c.set_params(kappa, csw)
+    return c, WilsonClover(dims, U, kappa, csw, bc_t=bc_t)
+
+
+def _maxrel(a, b):
+    return np.max(np.abs(a - b)) / np.max(np.abs(b))
+
+
+@pytest.mark.parametrize("prec", ["f32", "bf16"])
+@pytest.mark.parametrize("L", [1, 5, 12])
+def test_apply_lowp(pkg, prec, L):
+    c, op = _setup(pkg)
+    X = wi.gaussian_block(op.V, L, 302)
+    Y = c.apply(torch.from_numpy(X).cuda(), prec=prec).cpu().numpy()
+    err = _maxrel(Y, op.to_block(op.apply_A(op.from_block(X))))
+    _record(f"apply_{prec}_L{L}", err)
+    assert err < APPLY_TOL[prec]
+    c.close()
+
+
+@pytest.mark.parametrize("prec", ["f32", "bf16"])
+@pytest.mark.parametrize("j", [1, 2, 4, 12])
+def test_jacobi_lowp(pkg, prec, j):
+    c, op = _setup(pkg)
+    R = wi.gaussian_block(op.V, 4, 303)
+    Z = c.jacobi(torch.from_numpy(R).cuda(), j, prec=prec).cpu().numpy()
+    err = _maxrel(Z, op.to_block(jacobi_apply(op, op.from_block(R), j)))
+    _record(f"jacobi_{prec}_j{j}", err)
+    assert err < j * SWEEP_TOL[prec]
+    c.close()
+
+
+@pytest.mark.parametrize("prec", ["f32", "bf16"])
+def test_mixed_precision_solve_reaches_fp64_residual(pkg, prec):
+    w = wi.workload("lat8x16_L12_point")
+    U = wi.random_links(w["dims"], w["eps"], w["link_seed"])
+    c = pkg.Context(w["dims"], max_L=12)
+    c.set_links(U)
+    c.set_params(w["kappa"], w["csw"])
+    op = WilsonClover(w["dims"], U, w["kappa"], w["csw"])
+    B = wi.point_block(op.V, 12)
+    Bd = torch.from_numpy(B).cuda()
+    X64, i64 = c.solve(Bd, tol=1e-12, j=8, prec_inner="f64")
+    X, info = c.solve(Bd, tol=1e-12, j=8, prec_inner=prec)
+    assert info["status"] == "converged", info
+    tr = true_residual(op.A_mat, op.block_to_mat(B), op.block_to_mat(X.cpu().numpy()))
+    _record(f"solve_{prec}_true_residual", np.max(tr))
+    _record(f"solve_{prec}_iterations", info["iterations"])
+    _record(f"solve_f64_iterations", i64["iterations"])
+    assert np.max(tr) <= 1e-12
+    dx = float(torch.linalg.vector_norm(X - X64) / torch.linalg.vector_norm(X64))
+    _record(f"solve_{prec}_rel_diff_vs_f64", dx)
+    c.close()

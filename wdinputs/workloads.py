@@ -19,14 +19,18 @@ WORKLOADS = {
         dims=(8, 8, 8, 16), eps=0.3, link_seed=1002, kappa=0.135, csw=1.6,
         L=12, source="point", source_seed=0, j=(4, 8, 12, 16), tol=1e-12, bc_t=0,
     ),
-    # The paper's lattice size, 16^3 x 32, L sweep at j = 12.
+    # The paper's lattice size, 16^3 x 32, L sweep at j = 12 (kappa = 0.135
+    # stagnates near 1e-9 on this ensemble; 0.130 converges).
     "lat16x32_point": dict(
-        dims=(16, 16, 16, 32), eps=0.3, link_seed=1003, kappa=(0.130, 0.135), csw=1.6,
+        dims=(16, 16, 16, 32), eps=0.3, link_seed=1003, kappa=(0.130, 0.135), kappa_solve=0.130, csw=1.6,
         L=(1, 2, 3, 4, 6, 12), source="point", source_seed=0, j=(12,), tol=1e-12, bc_t=0,
     ),
     # 32^3 x 64 lattice (N = 25.2M), twelve point sources: the bandwidth headline.
+    # kappa = 0.135 lies past the critical hopping parameter of this ensemble
+    # (A has eigenvalues with negative real part and the solve does not
+    # converge), so solves use kappa_solve = 0.127, just below it.
     "lat32x64_L12_point": dict(
-        dims=(32, 32, 32, 64), eps=0.2, link_seed=1004, kappa=0.135, csw=1.6,
+        dims=(32, 32, 32, 64), eps=0.2, link_seed=1004, kappa=0.135, kappa_solve=0.127, csw=1.6,
         L=12, source="point", source_seed=0, j=(12,), tol=1e-12, bc_t=0,
     ),
 }
