@@ -45,6 +45,11 @@ def parse():
     p.add_argument("--kappa", type=float, default=None)
     p.add_argument("--hop-reps", type=int, default=20)
     p.add_argument("--no-compare", action="store_true", help="skip the per-precision solve comparison")
+    p.add_argument("--no-learned", action="store_true", help="skip the learned-preconditioner leg")
+    p.add_argument("--learn-pairs", type=int, default=24)
+    p.add_argument("--learn-steps", type=int, default=20)
+    p.add_argument("--kappa-heavy", type=float, default=0.12,
+                   help="second kappa (heavier quark) for the time-to-solution comparison; 0 skips it")
     p.add_argument("--no-cpu-baseline", action="store_true")
     p.add_argument("--kernels-only", action="store_true",
                    help="only the hopping-kernel launches and a plain copy (for rocprofv3 counter runs)")
@@ -52,9 +57,10 @@ def parse():
 
 
 def src_hash():
+    """Hash of the sources of the hopping kernels (the kernels whose HBM traffic is profiled)."""
     h = hashlib.sha256()
     d = os.path.join(ROOT, "paper_0907_3261_amd", "csrc")
-    for f in sorted(os.listdir(d)):
+    for f in ("wd_internal.h", "wd_dslash.hip"):
         with open(os.path.join(d, f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]
@@ -96,6 +102,86 @@ def time_hop(ctx, torch, V, L, mode, reps):
     e1.synchronize()
     del X, R, Y
     return e0.elapsed_time(e1) / reps
+
+
+def solve_record(info, L, X=None, Xref=None, torch=None, np=None):
+    d = {"status": info["status"], "iterations": info["total_iterations"], "cycles": info["cycles"],
+         "fallback": info["fallback"], "s_per_rhs": round(info["seconds"] / L, 5),
+         "true_residual_max": float(np.max(info["true_residual"])), "mvm_paper_per_col": int(info["mvm_paper"])}
+    if Xref is not None:
+        d["rel_diff_vs_f64"] = float(torch.linalg.vector_norm(X - Xref) / torch.linalg.vector_norm(Xref))
+    return d
+
+
+def compare_leg(ctx, torch, np, B, L, w, a):
+    """FP64, FP32 and BF16 Jacobi (j = a.j) solves from X = 0."""
+    out, Xref = {}, None
+    for prec in ("f64", "f32", "bf16"):
+        torch.cuda.synchronize()
+        X, info = ctx.solve(B, tol=w["tol"], j=a.j, prec_inner=prec)
+        torch.cuda.synchronize()
+        if prec == "f64":
+            Xref = X.clone()
+        out[f"jacobi{a.j}_{prec}"] = solve_record(info, L, X, Xref, torch, np)
+        print(f"[bench] jacobi {prec}: {out[f'jacobi{a.j}_{prec}']}", file=sys.stderr, flush=True)
+    return out, Xref
+
+
+def learned_setup(ctx, torch, B, V, L, a):
+    """Learned preconditioner: start from the factored degree-3 Neumann series, time one
+    application of M in FP64 and FP32, then train with Adam on pairs (A e, e), Gaussian e."""
+    out = {}
+    g = torch.Generator(device="cuda").manual_seed(12)
+    P = a.learn_pairs - a.learn_pairs % L
+    Ep = torch.complex(torch.randn((P, 12, V), generator=g, device="cuda", dtype=torch.float64),
+                       torch.randn((P, 12, V), generator=g, device="cuda", dtype=torch.float64))
+    Rp = torch.empty_like(Ep)
+    for i in range(0, P, L):
+        ctx.apply(Ep[i:i + L], Rp[i:i + L])
+    ctx.learned_init("neumann")
+    Z = torch.empty((L, 12, V), dtype=torch.complex128, device="cuda")
+    for prec, per_layer in (("f64", 576 + 384 * L), ("f32", 288 + 192 * L)):
+        ctx.learned_apply(B, Z, prec=prec)
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        reps = 5
+        e0.record(ctx.stream)
+        for _ in range(reps):
+            ctx.learned_apply(B, Z, prec=prec)
+        e1.record(ctx.stream)
+        e1.synchronize()
+        ms = e0.elapsed_time(e1) / reps
+        b = 3 * V * per_layer + (2 * V * 96 * L if prec == "f32" else 0)
+        out[f"apply_{prec}"] = {"ms": round(ms, 4), "alg_bytes": b, "GBs": round(b / (ms / 1e3) / 1e9, 1)}
+    thetas = {"neumann3": ctx.get_learned()}
+    t0 = time.time()
+    hist = ctx.learned_train(Rp, Ep, L, steps=a.learn_steps, lr=1e-3)
+    torch.cuda.synchronize()
+    out["train"] = {"pairs": P, "steps": a.learn_steps, "lr": 1e-3, "seconds": round(time.time() - t0, 3),
+                    "loss_first": float(hist[0]), "loss_last": float(hist[-1])}
+    thetas["trained"] = ctx.get_learned()
+    print(f"[bench] learned setup: {out}", file=sys.stderr, flush=True)
+    del Ep, Rp, Z
+    return out, thetas
+
+
+def learned_solves(ctx, torch, np, B, L, w, a, thetas, Xref):
+    """Solves with the learned M (Neumann start and trained weights) in FP64 and FP32; FP64
+    Jacobi j = a.j is the fallback of the FP32 form."""
+    from paper_0907_3261_amd import WD_PRECOND_LEARNED
+    out = {}
+    legs = [("neumann3", thetas["neumann3"], "f64"), ("trained", thetas["trained"], "f64"),
+            ("trained", thetas["trained"], "f32")]
+    for name, th, prec in legs:
+        if th is None:
+            continue
+        ctx.set_learned(th)
+        torch.cuda.synchronize()
+        X, info = ctx.solve(B, tol=w["tol"], j=a.j, precond=WD_PRECOND_LEARNED, prec_inner=prec)
+        torch.cuda.synchronize()
+        out[f"learned_{name}_{prec}"] = solve_record(info, L, X, Xref, torch, np)
+        print(f"[bench] learned {name} {prec}: {out[f'learned_{name}_{prec}']}", file=sys.stderr, flush=True)
+    return out
 
 
 def cpu_baseline(w, kappa):
@@ -205,23 +291,24 @@ def main():
               "avg_launch_ms": round(ms_apply, 4), "alg_bytes_per_launch": b_apply,
               "traffic": traffic_from_profiles(0)}
 
-    solves = {}
+    # time to solution per right-hand side: FP64 Jacobi (the plain form), low-precision Jacobi,
+    # learned M, at the workload's kappa and at a heavier quark mass (kappa_heavy)
+    solves, learned, thetas = {}, None, None
+    kappas = [kappa] + ([a.kappa_heavy] if a.kappa_heavy > 0 else [])
+    if not a.no_learned:
+        learned, thetas = learned_setup(ctx, torch, B, V, L, a)
     if not a.no_compare:
-        Xref = None
-        for prec in ("f64", "f32", "bf16"):
-            torch.cuda.synchronize()
-            X, info = ctx.solve(B, tol=w["tol"], j=a.j, prec_inner=prec)
-            torch.cuda.synchronize()
-            if prec == "f64":
-                Xref = X.clone()
-                dx = 0.0
-            else:
-                dx = float(torch.linalg.vector_norm(X - Xref) / torch.linalg.vector_norm(Xref))
-            solves[f"jacobi{a.j}_{prec}"] = {
-                "status": info["status"], "iterations": info["iterations"], "restarts": info["restarts"],
-                "s_per_rhs": round(info["seconds"] / L, 5), "true_residual_max": float(np.max(info["true_residual"])),
-                "mvm_paper_per_col": int(info["mvm_paper"]), "rel_diff_vs_f64": dx}
-            print(f"[bench] compare {prec}: {solves[f'jacobi{a.j}_{prec}']}", file=sys.stderr, flush=True)
+        for kp in kappas:
+            ctx.set_params(kp, w["csw"])
+            leg, Xref = compare_leg(ctx, torch, np, B, L, w, a)
+            if thetas is not None:
+                th = thetas
+                if kp != kappa:  # the Neumann start for this kappa; the weights were trained at the other
+                    ctx.learned_init("neumann")
+                    th = {"neumann3": ctx.get_learned(), "trained": None}
+                leg.update(learned_solves(ctx, torch, np, B, L, w, a, th, Xref))
+            solves[f"kappa{kp}"] = leg
+        ctx.set_params(kappa, w["csw"])
 
     cpu = None if a.no_cpu_baseline else cpu_baseline(w, kappa)
     ctx.close()
@@ -237,7 +324,7 @@ def main():
         "s_per_rhs": round(ms_step / 1e3 / L, 5),
         "converged": ok,
         "iterations": [i["iterations"] for i in infos],
-        "roofline": roof, "dslash": dslash, "solves": solves, "cpu_baseline": cpu,
+        "roofline": roof, "dslash": dslash, "solves": solves, "learned": learned, "cpu_baseline": cpu,
         "src_hash": src_hash(),
     }
     print(json.dumps(line), flush=True)

@@ -86,8 +86,8 @@ typedef struct wd_ctx wd_ctx;
 typedef struct wd_solve_opts {
     int j;                 /* Jacobi steps per application of M (>= 0); 0 means M = I */
     int precond;           /* WD_PRECOND_*; NONE forces j = 0 in the cost count */
-    int prec_inner;        /* WD_F64 / WD_F32 / WD_BF16 storage of the Jacobi preconditioner
-                              (the learned preconditioner always runs in FP32) */
+    int prec_inner;        /* WD_F64 / WD_F32 / WD_BF16 storage of the Jacobi preconditioner;
+                              WD_F64 / WD_F32 arithmetic of the learned one */
     int use_x0;            /* 1: X holds the initial guess; 0: start from X = 0 */
     int max_iter;          /* outer iterations per run; <= 0 means 5000 */
     int max_restarts;      /* true-residual restarts; < 0 means 3 */
@@ -101,6 +101,10 @@ typedef struct wd_solve_opts {
                               solver restarts from the FP64 true residual.  0: 1e-4 for FP32 and
                               1e-1 for BF16 storage of M (the learned M counts as FP32), no cycles
                               for FP64; < 0: no cycles */
+    int no_fallback;       /* 0: when a cycle of an inexact M stalls, diverges or breaks down, the
+                              solve starts again from X = 0 with the FP64 Jacobi preconditioner of
+                              the same j (M = I if j = 0); 1: the solve ends there with that
+                              status and X set to the cycle's best iterate */
 } wd_solve_opts;
 
 /* Results of bbicggr_solve. */
@@ -110,6 +114,7 @@ typedef struct wd_solve_info {
     int total_iterations;              /* over all restarts */
     int restarts;                      /* true-residual restarts made */
     int cycles;                        /* Krylov cycles run (1 without low-precision cycling) */
+    int fallback;                      /* 1 if the FP64 fallback of an inexact M was taken */
     long long mvm_paper;               /* per column, counted as in Table 1: 2(j+1)k + 1 per run */
     long long mvm_actual;              /* per column: hopping-term applications actually made */
     double seconds;                    /* wall time of the solve (device synchronised) */
@@ -228,9 +233,10 @@ int wd_set_learned(wd_ctx* ctx, const float* theta_host);
 #define WD_LEARNED_INIT_NEUMANN 1
 int wd_learned_init(wd_ctx* ctx, int kind);
 
-/* Z = M_theta R (FP64 in and out, FP32 arithmetic and storage inside); R and
- * Z are device block vectors of L columns and must not overlap. */
-int wd_learned_apply(wd_ctx* ctx, const void* R, void* Z, int L);
+/* Z = M_theta R (FP64 in and out); prec WD_F64 runs the layers in FP64, WD_F32
+ * in FP32 (arithmetic and intermediate storage).  R and Z are device block
+ * vectors of L columns and must not overlap. */
+int wd_learned_apply(wd_ctx* ctx, const void* R, void* Z, int L, int prec);
 
 /* Train theta on pairs (r, e) with A e ~ r: minimise the mean over columns of
  * ||M_theta r - e||^2 / ||e||^2 with Adam (lr, beta1 0.9, beta2 0.999) for

@@ -61,13 +61,15 @@ def _lu_solve(C: np.ndarray, rhs: np.ndarray):
 
 def block_bicggr(A, M, B: np.ndarray, tol: float, j: int, X0: np.ndarray | None = None,
                  max_iter: int = 5000, diverge_at: float = 1e2, stagnate_window: int = 200,
-                 callback=None):
+                 callback=None, Rt0: np.ndarray | None = None):
     """Solve A X = B (N x L, complex128) with preconditioned block BiCGGR.
 
     ``A`` and ``M`` are callables on N x L matrices; ``j`` is the number of
     Jacobi steps in ``M`` (used only for the cost count).  ``callback``, if
     given, is called once per iteration after X_{k+1} and R_{k+1} are formed
-    with a dict of the iteration's quantities.  Returns (X, info).
+    with a dict of the iteration's quantities.  ``Rt0`` is the shadow block
+    the algorithm of Sec. 2 leaves free; the default is R_0, the choice of
+    the paper's experiments (Sec. 3).  Returns (X, info).
     """
     B = np.asarray(B, dtype=np.complex128)
     N, L = B.shape
@@ -79,7 +81,7 @@ def block_bicggr(A, M, B: np.ndarray, tol: float, j: int, X0: np.ndarray | None 
     R = B - A(X)
     mvm += 1
     P = R.copy()
-    Rt = R.copy()
+    Rt = R.copy() if Rt0 is None else np.array(Rt0, dtype=np.complex128)
     F = M(R)
     mvm += j
     W = A(F)

@@ -47,12 +47,12 @@ class SolveOpts(ctypes.Structure):
     _fields_ = [("j", c_int), ("precond", c_int), ("prec_inner", c_int), ("use_x0", c_int),
                 ("max_iter", c_int), ("max_restarts", c_int), ("stagnate_window", c_int),
                 ("diverge_at", c_double), ("history", POINTER(c_double)), ("history_len", c_int),
-                ("cycle_tol", c_double)]
+                ("cycle_tol", c_double), ("no_fallback", c_int)]
 
 
 class SolveInfo(ctypes.Structure):
     _fields_ = [("status", c_int), ("iterations", c_int), ("total_iterations", c_int), ("restarts", c_int),
-                ("cycles", c_int),
+                ("cycles", c_int), ("fallback", c_int),
                 ("mvm_paper", c_longlong), ("mvm_actual", c_longlong), ("seconds", c_double),
                 ("bytes_alg", c_double),
                 ("true_residual", c_double * WD_MAX_L), ("recursive_residual", c_double * WD_MAX_L)]
@@ -81,7 +81,7 @@ SIGNATURES = [
     ("wd_set_learned", c_int, [c_void_p, c_void_p]),
     ("wd_learned_init", c_int, [c_void_p, c_int]),
     ("wd_get_learned", c_int, [c_void_p, c_void_p]),
-    ("wd_learned_apply", c_int, [c_void_p, c_void_p, c_void_p, c_int]),
+    ("wd_learned_apply", c_int, [c_void_p, c_void_p, c_void_p, c_int, c_int]),
     ("wd_learned_train", c_int, [c_void_p, c_void_p, c_void_p, c_int, c_int, c_int, c_double, c_void_p]),
     ("wd_learned_grad", c_int, [c_void_p, c_void_p, c_void_p, c_int, c_void_p, c_void_p]),
     ("wd_strerror", ctypes.c_char_p, [c_int]),
@@ -216,7 +216,8 @@ class Context:
 
     def solve(self, B, X=None, tol: float = 1e-12, j: int = 0, precond: int | None = None,
               prec_inner: str = "f64", max_iter: int = 0, max_restarts: int = -1, diverge_at: float = 0.0,
-              stagnate_window: int = 0, history_len: int = 0, cycle_tol: float = 0.0):
+              stagnate_window: int = 0, history_len: int = 0, cycle_tol: float = 0.0,
+              no_fallback: bool = False):
         """Preconditioned block BiCGGR; returns (X, info dict).  X, if given, is the initial guess."""
         L = B.shape[0]
         use_x0 = X is not None
@@ -229,12 +230,14 @@ class Context:
                       max_iter=int(max_iter), max_restarts=int(max_restarts),
                       stagnate_window=int(stagnate_window), diverge_at=float(diverge_at),
                       history=ctypes.cast(hist, POINTER(c_double)) if history_len else None,
-                      history_len=int(history_len), cycle_tol=float(cycle_tol))
+                      history_len=int(history_len), cycle_tol=float(cycle_tol),
+                      no_fallback=int(bool(no_fallback)))
         info = SolveInfo()
         code = _check(self._lib.bbicggr_solve(self._h, self._block(B), self._block(X, L), L, float(tol),
                                               ctypes.byref(o), ctypes.byref(info)), "bbicggr_solve")
         d = dict(code=code, status=STATUS_NAME.get(code, str(code)), iterations=info.iterations,
                  total_iterations=info.total_iterations, restarts=info.restarts, cycles=info.cycles,
+                 fallback=bool(info.fallback),
                  mvm_paper=info.mvm_paper,
                  mvm_actual=info.mvm_actual, seconds=info.seconds, bytes_alg=info.bytes_alg,
                  true_residual=np.array(info.true_residual[:L]),
@@ -267,11 +270,12 @@ class Context:
         _check(self._lib.wd_get_learned(self._h, a.ctypes.data), "wd_get_learned")
         return a
 
-    def learned_apply(self, R, Z=None):
+    def learned_apply(self, R, Z=None, prec: str = "f32"):
         L = R.shape[0]
         if Z is None:
             Z = self.empty_block(L)
-        _check(self._lib.wd_learned_apply(self._h, self._block(R), self._block(Z, L), L), "wd_learned_apply")
+        _check(self._lib.wd_learned_apply(self._h, self._block(R), self._block(Z, L), L, PREC[prec]),
+               "wd_learned_apply")
         return Z
 
     def learned_train(self, Rp, Ep, L: int, steps: int, lr: float = 1e-3):

@@ -359,10 +359,12 @@ struct Solver {
 
     int applyM(const double2* in, double2* out) {
         if (precond == WD_PRECOND_LEARNED) {
-            WD_TRY_HIP(launch_learned(c, in, out, L, c->stream));
+            WD_TRY_HIP(launch_learned(c, in, out, L, pin, c->ws[WS_JT], c->ws[WS_T2], c->stream));
             mvm_actual += WD_LEARNED_LAYERS;
-            // three FP32 layers: links 288 B per site each, FP64 in (first) and out (last)
-            bytes += (double)c->g.V * (3 * 288.0 + 192.0 * L + 4 * 96.0 * L + 192.0 * L);
+            // three layers: links read once per site, one input and one output block each
+            // (FP32: 288 + 192 L B per site, with the first input and last output in FP64)
+            bytes += pin == Prec::F64 ? (double)c->g.V * 3 * (576.0 + 384.0 * L)
+                                      : (double)c->g.V * (3 * (288.0 + 192.0 * L) + 2 * 96.0 * L);
             return WD_OK;
         }
         if (precond == WD_PRECOND_JACOBI && j > 0) {
@@ -409,10 +411,13 @@ int bbicggr_solve(wd_ctx* c, const void* Bv, void* Xv, int L, double tol, const 
         return WD_EINVAL;
     if (op.j < 0 || check_prec(op.prec_inner)) return WD_EINVAL;
     if (op.precond == WD_PRECOND_LEARNED) {
+        if (op.prec_inner == WD_BF16) return WD_EINVAL;
         if (!c->have_theta) return WD_ESTATE;
         int r0 = learned_ensure(c);
         if (r0) return r0;
     }
+    // FP64 fallback for an inexact M whose cycles stall: Jacobi in FP64 with the caller's j (M = I if 0)
+    const int fb_j = op.j;
     if (op.precond != WD_PRECOND_JACOBI) op.j = 0;
     const int max_iter = op.max_iter > 0 ? op.max_iter : 5000;
     const int max_restarts = op.max_restarts >= 0 ? op.max_restarts : 3;
@@ -461,12 +466,13 @@ int bbicggr_solve(wd_ctx* c, const void* Bv, void* Xv, int L, double tol, const 
     bool use_x0 = op.use_x0 != 0;
     double true_rel[WD_MAX_L] = {0}, rec_rel[WD_MAX_L] = {0};
     // Krylov cycles for an inexact M (low-precision storage of the Jacobi preconditioner)
-    const bool learned_M = op.precond == WD_PRECOND_LEARNED;
-    const bool inexact_M = learned_M || (op.precond == WD_PRECOND_JACOBI && op.j > 0 && op.prec_inner != WD_F64);
+    const bool inexact_M = op.prec_inner != WD_F64 &&
+                           (op.precond == WD_PRECOND_LEARNED || (op.precond == WD_PRECOND_JACOBI && op.j > 0));
     double cycle_tol = op.cycle_tol;
-    if (cycle_tol == 0.0) cycle_tol = inexact_M ? ((learned_M || op.prec_inner == WD_F32) ? 1e-4 : 1e-1) : -1.0;
-    const bool cycling = cycle_tol > 0.0;
-    const int cycle_stag = 20;   // iterations without improvement that end a cycle
+    if (cycle_tol == 0.0) cycle_tol = inexact_M ? (op.prec_inner == WD_F32 ? 1e-4 : 1e-1) : -1.0;
+    bool cycling = cycle_tol > 0.0;
+    bool fell_back = false;
+    const int cycle_stag = op.stagnate_window > 0 ? op.stagnate_window : 20;  // no-improvement limit of a cycle
     const int max_cycles = 200;
     double2* Xbest = S.ws(WS_T2);
     constexpr int kCycleEnd = 100;  // internal run status: restart from X
@@ -511,7 +517,10 @@ int bbicggr_solve(wd_ctx* c, const void* Bv, void* Xv, int L, double tol, const 
         const double res0 = res;
         double best = res;
         int best_k = 0;
-        bool have_best = false;  // Xbest holds an iterate better than the cycle's start
+        if (cycling) {  // Xbest: the best iterate of the cycle so far, starting with its initial X
+            WD_TRY_HIP(launch_copy(Xbest, X, N * L, st));
+            S.blocks(2);
+        }
         if (res <= tol) run_status = WD_OK;
         for (int k = 0; run_status == WD_NOT_CONVERGED && k < max_iter; ++k) {
             // alpha and zeta
@@ -565,7 +574,6 @@ int bbicggr_solve(wd_ctx* c, const void* Bv, void* Xv, int L, double tol, const 
                 if (cycling) {
                     WD_TRY_HIP(launch_copy(Xbest, X, N * L, st));
                     S.blocks(2);
-                    have_best = true;
                 }
             } else if (k + 1 - best_k >= window) {
                 run_status = WD_STAGNATED;
@@ -583,13 +591,24 @@ int bbicggr_solve(wd_ctx* c, const void* Bv, void* Xv, int L, double tol, const 
             S.blocks(6);
         }
         total_iters += iters;
-        // an inexact M: a cycle that stalled or blew up restarts from its best iterate, if it has one
-        if (cycling && cycles < max_cycles &&
-            (run_status == WD_STAGNATED || run_status == WD_DIVERGED || run_status == WD_BREAKDOWN ||
-             run_status == WD_NOT_CONVERGED) && have_best && best < res0) {
+        // an inexact M whose cycle stalled, blew up or broke down.  Unless the caller turned the
+        // fallback off, the solve starts again from X0 = 0 (so R~0 = R0 = B, as in a plain solve)
+        // with the FP64 Jacobi preconditioner: restarted from the inexact iterate, FP64 block
+        // BiCGGR close to the critical kappa can level off above a 1e-12 residual.  Without the
+        // fallback X returns to the cycle's best iterate.
+        if (cycling && (run_status == WD_STAGNATED || run_status == WD_DIVERGED || run_status == WD_BREAKDOWN ||
+                        run_status == WD_NOT_CONVERGED)) {
+            if (!op.no_fallback && run_status != WD_NOT_CONVERGED) {
+                S.precond = fb_j > 0 ? WD_PRECOND_JACOBI : WD_PRECOND_NONE;
+                S.j = fb_j;
+                S.pin = Prec::F64;
+                cycling = false;
+                fell_back = true;
+                use_x0 = false;
+                continue;
+            }
             WD_TRY_HIP(launch_copy(X, Xbest, N * L, st));
             S.blocks(2);
-            run_status = kCycleEnd;
         }
         if (run_status == kCycleEnd && cycles < max_cycles) {
             use_x0 = true;
@@ -628,6 +647,7 @@ int bbicggr_solve(wd_ctx* c, const void* Bv, void* Xv, int L, double tol, const 
         info->total_iterations = total_iters;
         info->restarts = restarts;
         info->cycles = cycles;
+        info->fallback = fell_back ? 1 : 0;
         info->mvm_paper = S.mvm_paper;
         info->mvm_actual = S.mvm_actual;
         info->seconds = secs;

@@ -317,7 +317,8 @@ inline double bytes_first_sweep(int L) { return 576.0 + 384.0 * L; }
 hipError_t launch_apply_A_lowp(wd_ctx* c, const double2* X, double2* Y, int L, Prec p, hipStream_t s);
 
 // ---- learned preconditioner (wd_learned.hip): Z = M_theta R, FP64 in and out
-hipError_t launch_learned(wd_ctx* c, const double2* R, double2* Z, int L, hipStream_t s);
+hipError_t launch_learned(wd_ctx* c, const double2* R, double2* Z, int L, Prec p, double2* t0, double2* t1,
+                          hipStream_t s);
 int learned_ensure(wd_ctx* c);
 
 // ---- block kernels (wd_blas.hip)

@@ -9,6 +9,7 @@
 // dl/dRe W_d + i dl/dIm W_d = 2 sum_{x,c,i} g(x) (S_d z)(x)^dag, the loss
 // mean_i ||y_i - e_i||^2 / ||e_i||^2 with its gradient, and Adam.
 #include <cmath>
+#include <cstdlib>
 #include <complex>
 #include <cstring>
 #include <vector>
@@ -71,36 +72,92 @@ __device__ __forceinline__ int neighbour(const Geom& g, int s, int d) {
     return c[0] + g.lx * (c[1] + g.ly * (c[2] + g.lz * c[3]));
 }
 
-// One layer for one column per thread.  W: 9 x 16 complex (row-major 4 x 4 per direction).
-template <class SI, class SO>
-__global__ void __launch_bounds__(256) k_layer(const Geom g, const float2* __restrict__ U,
+// One layer: thread (site, tile) accumulates CT columns, so each link and
+// weight is loaded once per tile.  SI / SO: storage of input / output, SL:
+// storage (and arithmetic precision) of the links.  W: 9 x 16 complex
+// (row-major 4 x 4 per direction), FP32.  Columns [c0 + tile*CT, + CT) of
+// the block vectors; every tile of the launch is complete.
+template <class SI, class SO, class SL, int CT>
+__global__ void __launch_bounds__(256) k_layer(const Geom g, const typename SL::P* __restrict__ U,
                                                const float2* __restrict__ W, const typename SI::P* __restrict__ Zin,
-                                               typename SO::P* __restrict__ Zout, const int L) {
+                                               typename SO::P* __restrict__ Zout, const int c0, const int ntile) {
+    using R = typename SL::R;
     const size_t V = g.V;
     const int s = blockIdx.x * 64 + threadIdx.x;
-    const int col = blockIdx.y * blockDim.y + threadIdx.y;
-    if (s >= g.V || col >= L) return;
-    const typename SI::P* zc = Zin + (size_t)col * 12 * V;
-    cx<float> acc[12];
+    const int tile = blockIdx.y * blockDim.y + threadIdx.y;
+    if (s >= g.V || tile >= ntile) return;
+    const int x = s % g.lx, y = (s / g.lx) % g.ly, z = (s / g.sxy) % g.lz, t = s / g.sxyz;
+    const int co[4] = {x, y, z, t};
+    const int ext[4] = {g.lx, g.ly, g.lz, g.lt};
+    const int str[4] = {1, g.lx, g.sxy, g.sxyz};
+    const size_t col0 = (size_t)(c0 + tile * CT);
+    cx<R> acc[CT][12];
 #pragma unroll
-    for (int k = 0; k < 12; ++k) acc[k] = {0.f, 0.f};
+    for (int c = 0; c < CT; ++c)
+#pragma unroll
+        for (int k = 0; k < 12; ++k) acc[c][k] = {R(0), R(0)};
     for (int d = 0; d < kND; ++d) {
-        cx<float> q[12];
-        shifted<SI>(U, zc, V, d, s, neighbour(g, s, d), q);
+        int nb = s, ls = s;
+        cx<R> u[9];
+        if (d > 0) {
+            const int mu = (d - 1) >> 1;
+            const bool fwd = (d & 1) != 0;
+            int cm = co[mu], off = str[mu];
+            if (fwd) nb = (cm + 1 == ext[mu]) ? s - (ext[mu] - 1) * off : s + off;
+            else nb = (cm == 0) ? s + (ext[mu] - 1) * off : s - off;
+            ls = fwd ? s : nb;
+#pragma unroll
+            for (int k = 0; k < 9; ++k) u[k] = SL::ld(U, (size_t)(mu * 9 + k) * V + ls);
+        }
         const float2* Wd = W + d * 16;
+        const bool fwd = (d & 1) != 0;
 #pragma unroll
-        for (int sp = 0; sp < 4; ++sp)
+        for (int c = 0; c < CT; ++c) {
+            const typename SI::P* zc = Zin + (col0 + c) * 12 * V;
+            // source spin tt: q = (U or U^dag or 1) psi_tt, then acc[sp] += W[sp][tt] q
 #pragma unroll
-            for (int t = 0; t < 4; ++t) {
-                const cx<float> w = StF32::ld(Wd, sp * 4 + t);
+            for (int tt = 0; tt < 4; ++tt) {
+                cx<R> p[3], q[3];
 #pragma unroll
-                for (int a = 0; a < 3; ++a) cfma(acc[3 * sp + a], w, q[3 * t + a]);
+                for (int b = 0; b < 3; ++b) {
+                    const auto v = SI::ld(zc, (size_t)(3 * tt + b) * V + nb);
+                    p[b] = {(R)v.re, (R)v.im};
+                }
+                if (d == 0) {
+#pragma unroll
+                    for (int a = 0; a < 3; ++a) q[a] = p[a];
+                } else {
+#pragma unroll
+                    for (int a = 0; a < 3; ++a) {
+                        cx<R> r = {R(0), R(0)};
+#pragma unroll
+                        for (int b = 0; b < 3; ++b) {
+                            if (fwd)
+                                cfma(r, u[a * 3 + b], p[b]);
+                            else
+                                cfmac(r, u[b * 3 + a], p[b]);
+                        }
+                        q[a] = r;
+                    }
+                }
+#pragma unroll
+                for (int sp = 0; sp < 4; ++sp) {
+                    const float2 wv = Wd[sp * 4 + tt];
+                    const cx<R> w = {(R)wv.x, (R)wv.y};
+#pragma unroll
+                    for (int a = 0; a < 3; ++a) cfma(acc[c][3 * sp + a], w, q[a]);
+                }
             }
+        }
     }
-    typename SO::P* oc = Zout + (size_t)col * 12 * V;
 #pragma unroll
-    for (int k = 0; k < 12; ++k)
-        SO::st(oc, (size_t)k * V + s, cx<typename SO::R>{(typename SO::R)acc[k].re, (typename SO::R)acc[k].im});
+    for (int c = 0; c < CT; ++c) {
+        typename SO::P* oc = Zout + (col0 + c) * 12 * V;
+#pragma unroll
+        for (int k = 0; k < 12; ++k)
+            SO::st(oc, (size_t)k * V + s,
+                   cx<typename SO::R>{(typename SO::R)acc[c][k].re, (typename SO::R)acc[c][k].im});
+    }
 }
 
 // Adjoint weights: W'_0 = W_0^dag, W'_{+mu} = W_{-mu}^dag, W'_{-mu} = W_{+mu}^dag
@@ -253,12 +310,47 @@ __global__ void k_adam(float2* __restrict__ theta, const double2* __restrict__ G
 
 inline unsigned nblk(size_t n, unsigned b) { return (unsigned)((n + b - 1) / b); }
 
+template <class SI, class SO, class SL, int CT>
+hipError_t launch_layer_ct(const wd_ctx* c, const typename SL::P* U, const float2* W, const void* in, void* out,
+                           int c0, int ntile, hipStream_t s) {
+    if (ntile <= 0) return hipSuccess;
+    const int ty = ntile < 4 ? ntile : 4;
+    dim3 block(64, ty), grid(nblk(c->g.V, 64), (ntile + ty - 1) / ty);
+    k_layer<SI, SO, SL, CT><<<grid, block, 0, s>>>(c->g, U, W, (const typename SI::P*)in, (typename SO::P*)out, c0,
+                                                   ntile);
+    return hipGetLastError();
+}
+
+// One layer over L columns: tiles of CT columns, then single columns for the rest.
+// Columns per thread: WDSOLVE_LEARN_CT (1, 2 or 4) if set, else 1.  At 32^3 x 64 with twelve
+// columns one column per thread is the fastest in both precisions (the wider tiles lose
+// occupancy to their accumulators, and FP64 with four columns spills).
+inline int layer_ct(bool f64) {
+    static const int env = [] {
+        const char* e = std::getenv("WDSOLVE_LEARN_CT");
+        const int v = e ? std::atoi(e) : 0;
+        return (v == 1 || v == 2 || v == 4) ? v : 0;
+    }();
+    (void)f64;
+    return env ? env : 1;
+}
+
+template <class SI, class SO, class SL>
+hipError_t launch_layer(const wd_ctx* c, const typename SL::P* U, const float2* W, const void* in, void* out, int L,
+                        hipStream_t s) {
+    const int ct = layer_ct(sizeof(typename SL::R) == 8);
+    const int nt = L / ct;
+    hipError_t e = hipSuccess;
+    if (ct == 4) e = launch_layer_ct<SI, SO, SL, 4>(c, U, W, in, out, 0, nt, s);
+    else if (ct == 2) e = launch_layer_ct<SI, SO, SL, 2>(c, U, W, in, out, 0, nt, s);
+    else e = launch_layer_ct<SI, SO, SL, 1>(c, U, W, in, out, 0, nt, s);
+    if (e == hipSuccess) e = launch_layer_ct<SI, SO, SL, 1>(c, U, W, in, out, nt * ct, L - nt * ct, s);
+    return e;
+}
+
 template <class SI, class SO>
 hipError_t launch_layer(const wd_ctx* c, const float2* W, const void* in, void* out, int L, hipStream_t s) {
-    const int ty = L < 4 ? L : 4;
-    dim3 block(64, ty), grid(nblk(c->g.V, 64), (L + ty - 1) / ty);
-    k_layer<SI, SO><<<grid, block, 0, s>>>(c->g, c->U32, W, (const typename SI::P*)in, (typename SO::P*)out, L);
-    return hipGetLastError();
+    return launch_layer<SI, SO, StF32>(c, c->U32, W, in, out, L, s);
 }
 
 constexpr int kWgBlocks = 64;
@@ -328,8 +420,18 @@ int learn_ws(wd_ctx* c, LearnWs& w) {
 
 namespace wd {
 
-// Z = M_theta R (FP64 in and out); uses the low-precision buffers as scratch
-hipError_t launch_learned(wd_ctx* c, const double2* R, double2* Z, int L, hipStream_t s) {
+// Z = M_theta R (FP64 in and out).  FP32: layers in FP32 with the
+// low-precision Jacobi buffers as scratch; FP64: layers in FP64 with two
+// FP64 workspace blocks (t0, t1) as scratch.
+hipError_t launch_learned(wd_ctx* c, const double2* R, double2* Z, int L, Prec p, double2* t0d, double2* t1d,
+                          hipStream_t s) {
+    if (p == Prec::F64) {
+        const double2* U = c->f.U;
+        hipError_t e = launch_layer<StF64, StF64, StF64>(c, U, c->theta, R, t0d, L, s);
+        if (e == hipSuccess) e = launch_layer<StF64, StF64, StF64>(c, U, c->theta + kND * 16, t0d, t1d, L, s);
+        if (e == hipSuccess) e = launch_layer<StF64, StF64, StF64>(c, U, c->theta + 2 * kND * 16, t1d, Z, L, s);
+        return e;
+    }
     float2* t0 = (float2*)c->lp[0];
     float2* t1 = (float2*)c->lp[1];
     hipError_t e = launch_layer<StF64, StF32>(c, c->theta, R, t0, L, s);
@@ -405,15 +507,17 @@ int wd_get_learned(wd_ctx* c, float* theta_host) {
     return WD_OK;
 }
 
-int wd_learned_apply(wd_ctx* c, const void* R, void* Z, int L) {
-    if (!c || !R || !Z || L < 1 || L > c->max_L) return WD_EINVAL;
+int wd_learned_apply(wd_ctx* c, const void* R, void* Z, int L, int prec) {
+    if (!c || !R || !Z || L < 1 || L > c->max_L || (prec != WD_F64 && prec != WD_F32)) return WD_EINVAL;
     if (!c->have_links || !c->have_theta) return WD_ESTATE;
     const size_t bytes = (size_t)12 * c->g.V * L * 16;
     const char *a = (const char*)R, *b = (const char*)Z;
     if (a < b + bytes && b < a + bytes) return WD_EINVAL;
     int r = learned_ensure(c);
     if (r) return r;
-    if (launch_learned(c, (const double2*)R, (double2*)Z, L, c->stream) != hipSuccess) return WD_EHIP;
+    if (launch_learned(c, (const double2*)R, (double2*)Z, L, (Prec)prec, c->ws[10], c->ws[11], c->stream) !=
+        hipSuccess)
+        return WD_EHIP;
     if (hipStreamSynchronize(c->stream) != hipSuccess) return WD_EHIP;
     return WD_OK;
 }
