@@ -170,8 +170,8 @@ def learned_solves(ctx, torch, np, B, L, w, a, thetas, Xref):
     Jacobi j = a.j is the fallback of the FP32 form."""
     from paper_0907_3261_amd import WD_PRECOND_LEARNED
     out = {}
-    legs = [("neumann3", thetas["neumann3"], "f64"), ("trained", thetas["trained"], "f64"),
-            ("trained", thetas["trained"], "f32")]
+    legs = [("neumann3", thetas["neumann3"], "f64"), ("neumann3", thetas["neumann3"], "f32"),
+            ("trained", thetas["trained"], "f64"), ("trained", thetas["trained"], "f32")]
     for name, th, prec in legs:
         if th is None:
             continue

@@ -4,6 +4,7 @@
 #pragma once
 
 #include <hip/hip_runtime.h>
+#include <cstdlib>
 #include <cstddef>
 #include <cstdint>
 
@@ -228,9 +229,16 @@ __device__ __forceinline__ int map_site(const Geom& g, const SiteMap& m, int b, 
 inline SiteMap make_site_map(const Geom& g, double bytes_site) {
     SiteMap m{};
     const double budget = 2.0 * 1024 * 1024;
+    // WDSOLVE_HOP_NY (tuning only) forces the y split when the lattice allows it
+    static const int forced_ny = [] {
+        const char* e = std::getenv("WDSOLVE_HOP_NY");
+        const int v = e ? std::atoi(e) : 0;
+        return (v == 1 || v == 2 || v == 4 || v == 8) ? v : 0;
+    }();
     for (int ny = 1; ny <= 8; ny *= 2) {
         const int nz = 8 / ny;
         if (g.ly < ny || g.lz < nz) continue;
+        if (forced_ny && ny != forced_ny && g.ly >= forced_ny && g.lz >= 8 / forced_ny) continue;
         const int rows = (g.ly + ny - 1) / ny;
         m.mode = 1;
         m.ny = ny;
