@@ -84,24 +84,29 @@ def traffic_from_profiles(mode: int):
     return None
 
 
-def time_hop(ctx, torch, V, L, mode, reps):
-    """Average duration of one hopping-kernel launch (mode 0: A X, 1: Jacobi sweep)."""
+def time_hop(ctx, torch, V, L, mode, reps, prec="f64"):
+    """Average duration of one hopping-kernel launch (mode 0: A X, 1: Jacobi sweep), from HIP
+    events on the library's stream around reps and 2 reps back-to-back launches (the difference
+    removes the once-per-call rounding of the inputs in FP32 / BF16)."""
     g = torch.Generator(device="cuda").manual_seed(11)
     X = torch.complex(torch.randn((L, 12, V), generator=g, device="cuda", dtype=torch.float64),
                       torch.randn((L, 12, V), generator=g, device="cuda", dtype=torch.float64))
     R = torch.complex(torch.randn((L, 12, V), generator=g, device="cuda", dtype=torch.float64),
                       torch.randn((L, 12, V), generator=g, device="cuda", dtype=torch.float64))
     Y = torch.empty_like(X)
-    ctx.hop_repeat(X, Y, 3, mode, R)
+    ctx.hop_repeat(X, Y, 3, mode, R, prec)
     st = ctx.stream
-    e0 = torch.cuda.Event(enable_timing=True)
-    e1 = torch.cuda.Event(enable_timing=True)
-    e0.record(st)
-    ctx.hop_repeat(X, Y, reps, mode, R)
-    e1.record(st)
-    e1.synchronize()
+    t = []
+    for n in (reps, 2 * reps):
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record(st)
+        ctx.hop_repeat(X, Y, n, mode, R, prec)
+        e1.record(st)
+        e1.synchronize()
+        t.append(e0.elapsed_time(e1))
     del X, R, Y
-    return e0.elapsed_time(e1) / reps
+    return (t[1] - t[0]) / reps
 
 
 def solve_record(info, L, X=None, Xref=None, torch=None, np=None):
@@ -293,6 +298,15 @@ def main():
 
     # time to solution per right-hand side: FP64 Jacobi (the plain form), low-precision Jacobi,
     # learned M, at the workload's kappa and at a heavier quark mass (kappa_heavy)
+    # the low-precision sweep of the mixed-precision Jacobi (FP32 accumulate)
+    lowp = {}
+    for prec, per_site in (("f32", 576 + 288 * L), ("bf16", 288 + 144 * L)):
+        ms_p = time_hop(ctx, torch, V, L, 1, a.hop_reps, prec)
+        b_p = V * per_site
+        lowp[prec] = {"avg_launch_ms": round(ms_p, 4), "alg_bytes_per_launch": b_p,
+                      "achieved": round(b_p / (ms_p / 1e3) / 1e9, 1), "frac": round(b_p / (ms_p / 1e3) / 1e9 / HBM_PEAK_GBS, 4)}
+    print(f"[bench] low-precision sweeps: {lowp}", file=sys.stderr, flush=True)
+
     solves, learned, thetas = {}, None, None
     kappas = [kappa] + ([a.kappa_heavy] if a.kappa_heavy > 0 else [])
     if not a.no_learned:
@@ -324,7 +338,7 @@ def main():
         "s_per_rhs": round(ms_step / 1e3 / L, 5),
         "converged": ok,
         "iterations": [i["iterations"] for i in infos],
-        "roofline": roof, "dslash": dslash, "solves": solves, "learned": learned, "cpu_baseline": cpu,
+        "roofline": roof, "dslash": dslash, "sweep_lowp": lowp, "solves": solves, "learned": learned, "cpu_baseline": cpu,
         "src_hash": src_hash(),
     }
     print(json.dumps(line), flush=True)

@@ -189,7 +189,10 @@ int bbicggr_solve(wd_ctx* ctx, const void* B, void* X, int L, double tol,
  * on the context stream, then wait.  mode 0 is Y = A X (as wd_apply);
  * mode 1 is one Jacobi sweep Y = A_D^{-1} (R + kappa H X) (the kernel that
  * jacobi_precond runs j - 1 times).  X, R, Y: device block vectors of L
- * columns in FP64 (prec must be WD_F64 here); R is ignored for mode 0. */
+ * columns in FP64; R is ignored for mode 0.  With prec WD_F32 or WD_BF16, X
+ * and R are first rounded into the library's low-precision buffers and the
+ * low-precision kernel runs on them (mode 0 writes Y in FP64; mode 1 keeps
+ * its low-precision output internal and leaves Y untouched). */
 int wd_hop_repeat(wd_ctx* ctx, const void* X, const void* R, void* Y, int L, int mode, int prec, int nrep);
 
 /* ---------------------------------------------------------------------------

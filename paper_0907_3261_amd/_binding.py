@@ -246,11 +246,11 @@ class Context:
             d["history"] = np.array(hist[:min(history_len, info.total_iterations + info.cycles + info.restarts)])
         return X, d
 
-    def hop_repeat(self, X, Y, nrep: int, mode: int = 0, R=None):
+    def hop_repeat(self, X, Y, nrep: int, mode: int = 0, R=None, prec: str = "f64"):
         """Launch the hopping kernel nrep times back to back (mode 0: A X, 1: Jacobi sweep)."""
         L = X.shape[0]
         r = self._block(R, L) if R is not None else None
-        _check(self._lib.wd_hop_repeat(self._h, self._block(X), r, self._block(Y, L), L, int(mode), WD_F64,
+        _check(self._lib.wd_hop_repeat(self._h, self._block(X), r, self._block(Y, L), L, int(mode), PREC[prec],
                                        int(nrep)), "wd_hop_repeat")
         return Y
 

@@ -298,10 +298,18 @@ int jacobi_precond(wd_ctx* c, const void* R, void* Z, int L, int j, int prec) {
 
 int wd_hop_repeat(wd_ctx* c, const void* X, const void* R, void* Y, int L, int mode, int prec, int nrep) {
     if (!c || !X || !Y || (mode == 1 && !R)) return WD_EINVAL;
-    if (L < 1 || L > c->max_L || prec != WD_F64 || nrep < 1 || (mode != 0 && mode != 1)) return WD_EINVAL;
+    if (L < 1 || L > c->max_L || check_prec(prec) || nrep < 1 || (mode != 0 && mode != 1)) return WD_EINVAL;
     if (!c->have_params) return WD_ESTATE;
     const size_t bytes = block_elems(c, L) * 16;
     if (overlap(X, Y, bytes) || (mode == 1 && overlap(R, Y, bytes))) return WD_EINVAL;
+    if (prec != WD_F64) {
+        int r = lowp_ensure(c);
+        if (r) return r;
+        WD_TRY_HIP(launch_hop_repeat_lowp(c, (const double2*)X, (const double2*)R, (double2*)Y, L, mode, (Prec)prec,
+                                          nrep, c->stream));
+        WD_TRY_HIP(hipStreamSynchronize(c->stream));
+        return WD_OK;
+    }
     for (int i = 0; i < nrep; ++i) {
         if (mode == 0)
             WD_TRY_HIP(launch_apply_A(c, (const double2*)X, (double2*)Y, L, c->stream));

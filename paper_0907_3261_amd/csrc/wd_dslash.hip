@@ -498,4 +498,26 @@ hipError_t launch_jacobi(wd_ctx* c, const double2* R, double2* Z, int L, int j, 
     return hipSuccess;
 }
 
+// Throughput measurement in FP32 / BF16 storage: X (and R) are rounded into
+// the low-precision buffers once, then the kernel runs nrep times on them.
+// mode 0: Y = A X with FP64 output; mode 1: a middle Jacobi sweep with
+// low-precision input and output (the output stays in the third buffer).
+hipError_t launch_hop_repeat_lowp(wd_ctx* c, const double2* X, const double2* R, double2* Y, int L, int mode, Prec p,
+                                  int nrep, hipStream_t s) {
+    const size_t n = (size_t)12 * c->g.V * L;
+    const int pi = p == Prec::F32 ? 1 : 2;
+    hipError_t e = launch_to_lowp(X, c->lp[0], p, n, s);
+    if (e == hipSuccess && mode == 1) e = launch_to_lowp(R, c->lp[2], p, n, s);
+    for (int i = 0; i < nrep && e == hipSuccess; ++i) {
+        if (mode == 0)
+            e = p == Prec::F32
+                    ? launch_hop_t<StF32, StF64, APPLY>(c->g, c->f.Uk[1], c->f.Tc[1], c->lp[0], nullptr, Y, L, s)
+                    : launch_hop_t<StBF16, StF64, APPLY>(c->g, c->f.Uk[2], c->f.Tc[2], c->lp[0], nullptr, Y, L, s);
+        else
+            e = p == Prec::F32 ? launch_sweep<StF32, StF32>(c, pi, c->lp[0], c->lp[2], c->lp[1], L, s)
+                               : launch_sweep<StBF16, StBF16>(c, pi, c->lp[0], c->lp[2], c->lp[1], L, s);
+    }
+    return e;
+}
+
 }  // namespace wd

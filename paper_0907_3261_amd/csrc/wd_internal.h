@@ -323,6 +323,8 @@ inline double bytes_sweep(int L) { return 1152.0 + 576.0 * L; }
 inline double bytes_first_sweep(int L) { return 576.0 + 384.0 * L; }
 // low precision application of A (diagnostic): Y (FP64) = A X computed in p
 hipError_t launch_apply_A_lowp(wd_ctx* c, const double2* X, double2* Y, int L, Prec p, hipStream_t s);
+hipError_t launch_hop_repeat_lowp(wd_ctx* c, const double2* X, const double2* R, double2* Y, int L, int mode, Prec p,
+                                  int nrep, hipStream_t s);
 
 // ---- learned preconditioner (wd_learned.hip): Z = M_theta R, FP64 in and out
 hipError_t launch_learned(wd_ctx* c, const double2* R, double2* Z, int L, Prec p, double2* t0, double2* t1,

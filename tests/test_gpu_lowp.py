@@ -87,6 +87,21 @@ def test_apply_lowp(pkg, prec, L):
 
 
 @pytest.mark.parametrize("prec", ["f32", "bf16"])
+def test_hop_repeat_lowp_runs_the_apply_kernel(pkg, prec):
+    """The throughput entry point in low precision launches the same kernel as wd_apply."""
+    c, op = _setup(pkg)
+    X = torch.from_numpy(wi.gaussian_block(op.V, 5, 304)).cuda()
+    R = torch.from_numpy(wi.gaussian_block(op.V, 5, 305)).cuda()
+    Y = torch.empty_like(X)
+    c.hop_repeat(X, Y, 2, 0, None, prec)
+    assert torch.equal(Y, c.apply(X, prec=prec))
+    Y2 = Y.clone()
+    c.hop_repeat(X, Y, 3, 1, R, prec)        # sweep mode keeps its output internal
+    assert torch.equal(Y, Y2)
+    c.close()
+
+
+@pytest.mark.parametrize("prec", ["f32", "bf16"])
 @pytest.mark.parametrize("j", [1, 2, 4, 12])
 def test_jacobi_lowp(pkg, prec, j):
     c, op = _setup(pkg)
