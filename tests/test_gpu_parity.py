@@ -66,7 +66,9 @@ def _maxrel(a, b):
     return np.max(np.abs(a - b)) / np.max(np.abs(b))
 
 
-# (16, 8, 4, 4) and (8, 16, 8, 3) take the pencil tile map (8 x 8 x 1 and 8 x 8 x 2 pencils)
+# Site maps exercised: (2, 2, 2, 2) the plain linear order (too small to split over the 8 XCDs);
+# (8, 16, 8, 3) the y x z = 1 x 8 split; (4, 4, 4, 4), (8, 6, 4, 10) and (16, 8, 4, 4) the 2 x 4
+# split with one z plane per XCD; (3, 4, 5, 6) the 2 x 4 split with uneven y and z ranges.
 CASES = [((4, 4, 4, 4), 0), ((3, 4, 5, 6), 1), ((2, 2, 2, 2), 0), ((8, 6, 4, 10), 1), ((16, 8, 4, 4), 1),
          ((8, 16, 8, 3), 0)]
 
@@ -265,11 +267,11 @@ def test_solve_first_iterations_match_oracle(pkg, k):
 
 
 def test_solve_point_sources_jacobi_oracle_residual(pkg):
-    """8^3 x 16, kappa 0.135, c_SW 1.6, twelve point sources, Jacobi j = 4 and 12."""
+    """8^3 x 16, kappa 0.135, c_SW 1.6, twelve point sources, Jacobi j = 4, 8, 12, 16."""
     w, c, op = _workload_ctx(pkg, "lat8x16_L12_point")
     B = wi.point_block(op.V, 12)
     Bm = op.block_to_mat(B)
-    for j in (4, 12):
+    for j in w["j"]:
         X, info = c.solve(_dev(B), tol=1e-12, j=j)
         assert info["status"] == "converged", info
         assert np.max(info["true_residual"]) <= 1e-12
@@ -278,6 +280,7 @@ def test_solve_point_sources_jacobi_oracle_residual(pkg):
         assert np.max(tr) <= 1e-12
         if info["restarts"] == 0:
             assert info["mvm_paper"] == 2 * (j + 1) * info["iterations"] + 1
+        _say(f"j={j}: k={info['iterations']} mvm/L={info['mvm_paper']} restarts={info['restarts']}")
     c.close()
 
 
