@@ -77,8 +77,11 @@ def traffic_from_profiles(mode: int):
         if d.get("src_hash") != src_hash():
             return None
         for k, v in d.get("bytes_per_launch", {}).items():
-            if k.startswith("void k_hop<StF64, StF64") and k.rstrip().endswith(f", {mode}>"):
-                return v
+            # template arguments of the hop kernel: storage in, storage out, columns, mode, stream policy
+            if k.startswith("void k_hop<StF64, StF64,"):
+                args = [a.strip() for a in k[k.index("<") + 1:k.rindex(">")].split(",")]
+                if len(args) >= 4 and args[3] == str(mode):
+                    return v
     except Exception:
         return None
     return None
