@@ -48,6 +48,8 @@ def parse():
     p.add_argument("--no-learned", action="store_true", help="skip the learned-preconditioner leg")
     p.add_argument("--learn-pairs", type=int, default=24)
     p.add_argument("--learn-steps", type=int, default=20)
+    p.add_argument("--learn-snaps", type=int, default=3, help="solver snapshots used as training pairs")
+    p.add_argument("--snap-every", type=int, default=15)
     p.add_argument("--kappa-heavy", type=float, default=0.12,
                    help="second kappa (heavier quark) for the time-to-solution comparison; 0 skips it")
     p.add_argument("--no-cpu-baseline", action="store_true")
@@ -135,17 +137,33 @@ def compare_leg(ctx, torch, np, B, L, w, a):
     return out, Xref
 
 
-def learned_setup(ctx, torch, B, V, L, a):
+def learned_setup(ctx, torch, np, B, V, L, w, a):
     """Learned preconditioner: start from the factored degree-3 Neumann series, time one
-    application of M in FP64 and FP32, then train with Adam on pairs (A e, e), Gaussian e."""
+    application of M in FP64 and FP32, then train with Adam on pairs that the solver generates
+    (snapshots X_k of an FP64 Jacobi solve: r = B - A X_k, e = X - X_k) together with pairs
+    (A e, e) for Gaussian e."""
     out = {}
     g = torch.Generator(device="cuda").manual_seed(12)
-    P = a.learn_pairs - a.learn_pairs % L
-    Ep = torch.complex(torch.randn((P, 12, V), generator=g, device="cuda", dtype=torch.float64),
-                       torch.randn((P, 12, V), generator=g, device="cuda", dtype=torch.float64))
+    P = a.learn_pairs - a.learn_pairs % L           # Gaussian pairs
+    S = a.learn_snaps                               # snapshot blocks of L columns
+    Ep = torch.empty(((P // L + S) * L, 12, V), dtype=torch.complex128, device="cuda")
     Rp = torch.empty_like(Ep)
+    Ep[:P] = torch.complex(torch.randn((P, 12, V), generator=g, device="cuda", dtype=torch.float64),
+                           torch.randn((P, 12, V), generator=g, device="cuda", dtype=torch.float64))
     for i in range(0, P, L):
         ctx.apply(Ep[i:i + L], Rp[i:i + L])
+    if S > 0:
+        Xs = torch.empty((S * L, 12, V), dtype=torch.complex128, device="cuda")
+        X, info = ctx.solve(B, tol=w["tol"], j=a.j, x_snap=Xs, snap_every=a.snap_every)
+        ns = info["snapshots"]
+        if ns > 0:
+            r, e = ctx.learned_pairs(B, X, Xs[:ns * L])
+            Rp[P:P + ns * L] = r
+            Ep[P:P + ns * L] = e
+            del r, e
+        Rp, Ep = Rp[:P + ns * L], Ep[:P + ns * L]
+        out["solver_pairs"] = {"snapshots": ns, "every": a.snap_every, "columns": ns * L}
+        del Xs, X
     ctx.learned_init("neumann")
     Z = torch.empty((L, 12, V), dtype=torch.complex128, device="cuda")
     for prec, per_layer in (("f64", 576 + 384 * L), ("f32", 288 + 192 * L)):
@@ -162,12 +180,19 @@ def learned_setup(ctx, torch, B, V, L, a):
         b = 3 * V * per_layer + (2 * V * 96 * L if prec == "f32" else 0)
         out[f"apply_{prec}"] = {"ms": round(ms, 4), "alg_bytes": b, "GBs": round(b / (ms / 1e3) / 1e9, 1)}
     thetas = {"neumann3": ctx.get_learned()}
-    t0 = time.time()
-    hist = ctx.learned_train(Rp, Ep, L, steps=a.learn_steps, lr=1e-3)
-    torch.cuda.synchronize()
-    out["train"] = {"pairs": P, "steps": a.learn_steps, "lr": 1e-3, "seconds": round(time.time() - t0, 3),
-                    "loss_first": float(hist[0]), "loss_last": float(hist[-1])}
-    thetas["trained"] = ctx.get_learned()
+    # two trainings from the Neumann start: Gaussian pairs only, and solver pairs with them
+    for name, (r, e) in (("trained_gauss", (Rp[:P], Ep[:P])), ("trained_solver", (Rp, Ep))):
+        if name == "trained_solver" and r.shape[0] == P:
+            continue
+        ctx.set_learned(thetas["neumann3"])
+        t0 = time.time()
+        hist = ctx.learned_train(r, e, L, steps=a.learn_steps, lr=1e-3)
+        torch.cuda.synchronize()
+        nb = r.shape[0] // L          # batches cycle, so compare whole passes over the pairs
+        out[name] = {"pairs": int(r.shape[0]), "steps": a.learn_steps, "lr": 1e-3,
+                     "seconds": round(time.time() - t0, 3),
+                     "loss_first_pass": float(np.mean(hist[:nb])), "loss_last_pass": float(np.mean(hist[-nb:]))}
+        thetas[name] = ctx.get_learned()
     print(f"[bench] learned setup: {out}", file=sys.stderr, flush=True)
     del Ep, Rp, Z
     return out, thetas
@@ -178,8 +203,8 @@ def learned_solves(ctx, torch, np, B, L, w, a, thetas, Xref):
     Jacobi j = a.j is the fallback of the FP32 form."""
     from paper_0907_3261_amd import WD_PRECOND_LEARNED
     out = {}
-    legs = [("neumann3", thetas["neumann3"], "f64"), ("neumann3", thetas["neumann3"], "f32"),
-            ("trained", thetas["trained"], "f64"), ("trained", thetas["trained"], "f32")]
+    legs = [("neumann3", thetas["neumann3"], "f64"), ("neumann3", thetas["neumann3"], "f32")]
+    legs += [(k, thetas[k], "f64") for k in ("trained_gauss", "trained_solver") if thetas.get(k) is not None]
     for name, th, prec in legs:
         if th is None:
             continue
@@ -313,7 +338,7 @@ def main():
     solves, learned, thetas = {}, None, None
     kappas = [kappa] + ([a.kappa_heavy] if a.kappa_heavy > 0 else [])
     if not a.no_learned:
-        learned, thetas = learned_setup(ctx, torch, B, V, L, a)
+        learned, thetas = learned_setup(ctx, torch, np, B, V, L, w, a)
     if not a.no_compare:
         for kp in kappas:
             ctx.set_params(kp, w["csw"])
@@ -322,7 +347,7 @@ def main():
                 th = thetas
                 if kp != kappa:  # the Neumann start for this kappa; the weights were trained at the other
                     ctx.learned_init("neumann")
-                    th = {"neumann3": ctx.get_learned(), "trained": None}
+                    th = {"neumann3": ctx.get_learned()}
                 leg.update(learned_solves(ctx, torch, np, B, L, w, a, th, Xref))
             solves[f"kappa{kp}"] = leg
         ctx.set_params(kappa, w["csw"])

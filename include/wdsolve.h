@@ -105,6 +105,12 @@ typedef struct wd_solve_opts {
                               solve starts again from X = 0 with the FP64 Jacobi preconditioner of
                               the same j (M = I if j = 0); 1: the solve ends there with that
                               status and X set to the cycle's best iterate */
+    void* x_snap;          /* optional device buffer of snap_count block vectors of L columns:
+                              the iterate X_k is copied into slot i after outer iteration
+                              k = (i + 1) * snap_every (counted over all runs of the solve), for
+                              training pairs of the learned preconditioner (wd_learned_pairs) */
+    int snap_count;        /* slots in x_snap (0: no snapshots) */
+    int snap_every;        /* iterations between snapshots (>= 1 when snap_count > 0) */
 } wd_solve_opts;
 
 /* Results of bbicggr_solve. */
@@ -115,6 +121,7 @@ typedef struct wd_solve_info {
     int restarts;                      /* true-residual restarts made */
     int cycles;                        /* Krylov cycles run (1 without low-precision cycling) */
     int fallback;                      /* 1 if the FP64 fallback of an inexact M was taken */
+    int snapshots;                     /* iterates copied into opts->x_snap */
     long long mvm_paper;               /* per column, counted as in Table 1: 2(j+1)k + 1 per run */
     long long mvm_actual;              /* per column: hopping-term applications actually made */
     double seconds;                    /* wall time of the solve (device synchronised) */
@@ -249,6 +256,16 @@ int wd_learned_apply(wd_ctx* ctx, const void* R, void* Z, int L, int prec);
  * (host, may be NULL) receives one loss per step. */
 int wd_learned_train(wd_ctx* ctx, const void* Rp, const void* Ep, int n_pairs, int L,
                      int steps, double lr, float* loss_hist);
+
+/* Training pairs generated by the solver itself: for each of the n snapshots
+ * X_k in Xsnap (device, n block vectors of L columns, as written by
+ * bbicggr_solve with x_snap), Rp_k = B - A X_k and Ep_k = X - X_k, where X is
+ * the converged solution of A X = B.  Rp and Ep are device buffers of n * L
+ * columns (the layout wd_learned_train takes); none of the buffers may
+ * overlap.  A pair satisfies A e = r exactly (up to rounding): e is the
+ * correction that the residual r asks for. */
+int wd_learned_pairs(wd_ctx* ctx, const void* B, const void* X, const void* Xsnap, int n, int L, void* Rp,
+                     void* Ep);
 
 /* Copy the current theta to host memory (3*9*16 complex64). */
 int wd_get_learned(wd_ctx* ctx, float* theta_host);

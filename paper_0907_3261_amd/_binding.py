@@ -47,12 +47,13 @@ class SolveOpts(ctypes.Structure):
     _fields_ = [("j", c_int), ("precond", c_int), ("prec_inner", c_int), ("use_x0", c_int),
                 ("max_iter", c_int), ("max_restarts", c_int), ("stagnate_window", c_int),
                 ("diverge_at", c_double), ("history", POINTER(c_double)), ("history_len", c_int),
-                ("cycle_tol", c_double), ("no_fallback", c_int)]
+                ("cycle_tol", c_double), ("no_fallback", c_int), ("x_snap", c_void_p), ("snap_count", c_int),
+                ("snap_every", c_int)]
 
 
 class SolveInfo(ctypes.Structure):
     _fields_ = [("status", c_int), ("iterations", c_int), ("total_iterations", c_int), ("restarts", c_int),
-                ("cycles", c_int), ("fallback", c_int),
+                ("cycles", c_int), ("fallback", c_int), ("snapshots", c_int),
                 ("mvm_paper", c_longlong), ("mvm_actual", c_longlong), ("seconds", c_double),
                 ("bytes_alg", c_double),
                 ("true_residual", c_double * WD_MAX_L), ("recursive_residual", c_double * WD_MAX_L)]
@@ -80,6 +81,7 @@ SIGNATURES = [
     ("wd_small_solve", c_int, [c_void_p, c_void_p, c_void_p, c_int, c_void_p]),
     ("wd_set_learned", c_int, [c_void_p, c_void_p]),
     ("wd_learned_init", c_int, [c_void_p, c_int]),
+    ("wd_learned_pairs", c_int, [c_void_p, c_void_p, c_void_p, c_void_p, c_int, c_int, c_void_p, c_void_p]),
     ("wd_get_learned", c_int, [c_void_p, c_void_p]),
     ("wd_learned_apply", c_int, [c_void_p, c_void_p, c_void_p, c_int, c_int]),
     ("wd_learned_train", c_int, [c_void_p, c_void_p, c_void_p, c_int, c_int, c_int, c_double, c_void_p]),
@@ -196,6 +198,16 @@ class Context:
             raise ValueError("column count mismatch")
         return _dptr(t)
 
+    def _snap_ptr(self, t, L):
+        """x_snap: complex128 tensor of shape (n * L, 12, V); n snapshots of L columns."""
+        if t is None:
+            return None
+        torch = _torch()
+        if t.dtype != torch.complex128 or t.dim() != 3 or t.shape[1] != 12 or t.shape[2] != self.V or \
+                t.shape[0] % L or not t.is_contiguous():
+            raise ValueError("x_snap must be a contiguous complex128 tensor of shape (n * L, 12, V)")
+        return _dptr(t)
+
     def empty_block(self, L: int):
         return _torch().empty((L, 12, self.V), dtype=_torch().complex128, device=self.device)
 
@@ -217,7 +229,7 @@ class Context:
     def solve(self, B, X=None, tol: float = 1e-12, j: int = 0, precond: int | None = None,
               prec_inner: str = "f64", max_iter: int = 0, max_restarts: int = -1, diverge_at: float = 0.0,
               stagnate_window: int = 0, history_len: int = 0, cycle_tol: float = 0.0,
-              no_fallback: bool = False):
+              no_fallback: bool = False, x_snap=None, snap_every: int = 0):
         """Preconditioned block BiCGGR; returns (X, info dict).  X, if given, is the initial guess."""
         L = B.shape[0]
         use_x0 = X is not None
@@ -231,13 +243,15 @@ class Context:
                       stagnate_window=int(stagnate_window), diverge_at=float(diverge_at),
                       history=ctypes.cast(hist, POINTER(c_double)) if history_len else None,
                       history_len=int(history_len), cycle_tol=float(cycle_tol),
-                      no_fallback=int(bool(no_fallback)))
+                      no_fallback=int(bool(no_fallback)),
+                      x_snap=self._snap_ptr(x_snap, L), snap_count=(x_snap.shape[0] // L) if x_snap is not None else 0,
+                      snap_every=int(snap_every))
         info = SolveInfo()
         code = _check(self._lib.bbicggr_solve(self._h, self._block(B), self._block(X, L), L, float(tol),
                                               ctypes.byref(o), ctypes.byref(info)), "bbicggr_solve")
         d = dict(code=code, status=STATUS_NAME.get(code, str(code)), iterations=info.iterations,
                  total_iterations=info.total_iterations, restarts=info.restarts, cycles=info.cycles,
-                 fallback=bool(info.fallback),
+                 fallback=bool(info.fallback), snapshots=info.snapshots,
                  mvm_paper=info.mvm_paper,
                  mvm_actual=info.mvm_actual, seconds=info.seconds, bytes_alg=info.bytes_alg,
                  true_residual=np.array(info.true_residual[:L]),
@@ -264,6 +278,16 @@ class Context:
         """theta := identity (M = 1) or the factored degree-3 Neumann series of (1 - kappa H)^-1."""
         k = {"identity": WD_LEARNED_INIT_IDENTITY, "neumann": WD_LEARNED_INIT_NEUMANN}[kind]
         _check(self._lib.wd_learned_init(self._h, k), "wd_learned_init")
+
+    def learned_pairs(self, B, X, Xsnap):
+        """Pairs (Rp, Ep) = (B - A X_k, X - X_k) from the solver's snapshots X_k (Xsnap: (n L, 12, V))."""
+        L = B.shape[0]
+        n = Xsnap.shape[0] // L
+        Rp = _torch().empty_like(Xsnap)
+        Ep = _torch().empty_like(Xsnap)
+        _check(self._lib.wd_learned_pairs(self._h, self._block(B), self._block(X, L), self._snap_ptr(Xsnap, L),
+                                          n, L, _dptr(Rp), _dptr(Ep)), "wd_learned_pairs")
+        return Rp, Ep
 
     def get_learned(self) -> np.ndarray:
         a = np.empty((3, 9, 4, 4), dtype=np.complex64)

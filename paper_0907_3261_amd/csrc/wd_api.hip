@@ -28,6 +28,13 @@ bool overlap(const void* a, const void* b, size_t bytes) {
     return pa < pb + bytes && pb < pa + bytes;
 }
 
+// [a, a + na) and [b, b + nb) share a byte
+bool ranges_overlap(const void* a, size_t na, const void* b, size_t nb) {
+    const char* pa = (const char*)a;
+    const char* pb = (const char*)b;
+    return pa < pb + nb && pb < pa + na;
+}
+
 int dev_alloc(void** p, size_t bytes) {
     if (hipMalloc(p, bytes) != hipSuccess) {
         *p = nullptr;
@@ -343,6 +350,27 @@ int wd_small_solve(wd_ctx* c, const void* M, const void* RHS, int L, void* Z) {
     return st ? WD_BREAKDOWN : WD_OK;
 }
 
+int wd_learned_pairs(wd_ctx* c, const void* B, const void* X, const void* Xsnap, int n, int L, void* Rp, void* Ep) {
+    if (!c || !B || !X || !Xsnap || !Rp || !Ep || n < 1 || L < 1 || L > c->max_L) return WD_EINVAL;
+    if (!c->have_params) return WD_ESTATE;
+    const size_t N = (size_t)12 * c->g.V, blk = N * L * 16, all = blk * n;
+    const void* in[3] = {B, X, Xsnap};
+    const size_t in_n[3] = {blk, blk, all};
+    for (int i = 0; i < 3; ++i)
+        if (ranges_overlap(in[i], in_n[i], Rp, all) || ranges_overlap(in[i], in_n[i], Ep, all)) return WD_EINVAL;
+    if (ranges_overlap(Rp, all, Ep, all)) return WD_EINVAL;
+    for (int k = 0; k < n; ++k) {
+        const double2* xs = (const double2*)Xsnap + (size_t)k * N * L;
+        double2* r = (double2*)Rp + (size_t)k * N * L;
+        double2* e = (double2*)Ep + (size_t)k * N * L;
+        WD_TRY_HIP(launch_apply_A(c, xs, c->ws[WS_T1], L, c->stream));                  // A X_k
+        WD_TRY_HIP(launch_axpby_block((const double2*)B, c->ws[WS_T1], r, N * L, c->stream));  // B - A X_k
+        WD_TRY_HIP(launch_axpby_block((const double2*)X, xs, e, N * L, c->stream));      // e = X - X_k
+    }
+    WD_TRY_HIP(hipStreamSynchronize(c->stream));
+    return WD_OK;
+}
+
 // ---------------------------------------------------------------------------
 // Preconditioned block BiCGGR
 // ---------------------------------------------------------------------------
@@ -418,6 +446,7 @@ int bbicggr_solve(wd_ctx* c, const void* Bv, void* Xv, int L, double tol, const 
     if (op.precond != WD_PRECOND_NONE && op.precond != WD_PRECOND_JACOBI && op.precond != WD_PRECOND_LEARNED)
         return WD_EINVAL;
     if (op.j < 0 || check_prec(op.prec_inner)) return WD_EINVAL;
+    if (op.snap_count < 0 || (op.snap_count > 0 && (!op.x_snap || op.snap_every < 1))) return WD_EINVAL;
     if (op.precond == WD_PRECOND_LEARNED) {
         if (op.prec_inner == WD_BF16) return WD_EINVAL;
         if (!c->have_theta) return WD_ESTATE;
@@ -433,6 +462,10 @@ int bbicggr_solve(wd_ctx* c, const void* Bv, void* Xv, int L, double tol, const 
     const double diverge_at = op.diverge_at > 0 ? op.diverge_at : 1e2;
     const size_t N = (size_t)12 * c->g.V;
     if (overlap(Bv, Xv, N * L * 16)) return WD_EINVAL;
+    const size_t blk_bytes = N * L * 16;
+    if (op.snap_count > 0 && (ranges_overlap(op.x_snap, blk_bytes * op.snap_count, Bv, blk_bytes) ||
+                              ranges_overlap(op.x_snap, blk_bytes * op.snap_count, Xv, blk_bytes)))
+        return WD_EINVAL;
     if (op.prec_inner != WD_F64 && op.precond == WD_PRECOND_JACOBI) {
         int r = lowp_ensure(c);
         if (r) return r;
@@ -471,6 +504,8 @@ int bbicggr_solve(wd_ctx* c, const void* Bv, void* Xv, int L, double tol, const 
     Ctl* hc = reinterpret_cast<Ctl*>(c->host_ctl);
     int status = WD_NOT_CONVERGED;
     int iters = 0, total_iters = 0, restarts = 0, cycles = 0, hist_pos = 0;
+    long long snap_clock = 0;  // outer iterations over all runs, for the snapshots
+    int snaps = 0;
     bool use_x0 = op.use_x0 != 0;
     double true_rel[WD_MAX_L] = {0}, rec_rel[WD_MAX_L] = {0};
     // Krylov cycles for an inexact M (low-precision storage of the Jacobi preconditioner)
@@ -551,6 +586,11 @@ int bbicggr_solve(wd_ctx* c, const void* Bv, void* Xv, int L, double tol, const 
                 break;
             }
             iters = k + 1;
+            ++snap_clock;
+            if (snaps < op.snap_count && snap_clock % op.snap_every == 0) {
+                WD_TRY_HIP(launch_copy((double2*)op.x_snap + (size_t)snaps * N * L, X, N * L, st));
+                ++snaps;
+            }
             res = 0.0;
             bool nan = (hc->status & 4) != 0;
             for (int i = 0; i < L; ++i) {
@@ -656,6 +696,7 @@ int bbicggr_solve(wd_ctx* c, const void* Bv, void* Xv, int L, double tol, const 
         info->restarts = restarts;
         info->cycles = cycles;
         info->fallback = fell_back ? 1 : 0;
+        info->snapshots = snaps;
         info->mvm_paper = S.mvm_paper;
         info->mvm_actual = S.mvm_actual;
         info->seconds = secs;

@@ -60,4 +60,4 @@ def test_struct_layouts_match_header():
         body = re.sub(r"/\*.*?\*/", "", body, flags=re.S)
         fields = re.findall(r"(\w+)(?:\[\w+\])?\s*;", body)
         assert fields == [f for f, _ in cls._fields_]
-    assert ctypes.sizeof(SolveInfo) == 6 * 4 + 8 * 2 + 8 + 8 + 2 * 16 * 8
+    assert ctypes.sizeof(SolveInfo) == 7 * 4 + 4 + 8 * 2 + 8 + 8 + 2 * 16 * 8

@@ -174,3 +174,28 @@ def test_training_lowers_loss_and_solves(pkg, prec):
     if prec == "f64":
         assert info["cycles"] == 1 and not info["fallback"]
     c.close()
+
+
+def test_solver_snapshots_and_pairs(pkg):
+    """Training pairs generated by the solver: snapshots of its iterates X_k, then
+    r = B - A X_k and e = X - X_k, checked against separate runs and the oracle."""
+    dims = (4, 6, 4, 8)
+    c, op = _ctx(pkg, dims, kappa=0.12, csw=1.6, bc_t=1)
+    L, n, every = 3, 3, 2
+    B = torch.from_numpy(wi.gaussian_block(op.V, L, 410)).cuda()
+    Xs = torch.zeros((n * L, 12, op.V), dtype=torch.complex128, device="cuda")
+    X, info = c.solve(B, tol=1e-12, j=1, x_snap=Xs, snap_every=every)
+    assert info["status"] == "converged" and info["snapshots"] == n, info
+    for i in range(n):
+        Xk, _ = c.solve(B, tol=1e-30, j=1, max_iter=every * (i + 1), max_restarts=0)
+        assert torch.equal(Xs[i * L:(i + 1) * L], Xk)
+    Rp, Ep = c.learned_pairs(B, X, Xs)
+    Bh, Xh = B.cpu().numpy(), X.cpu().numpy()
+    for i in range(n):
+        xk = Xs[i * L:(i + 1) * L].cpu().numpy()
+        r_o = Bh - op.to_block(op.apply_A(op.from_block(xk)))
+        assert _maxrel(Rp[i * L:(i + 1) * L].cpu().numpy(), r_o) < 1e-13
+        assert np.array_equal(Ep[i * L:(i + 1) * L].cpu().numpy(), Xh - xk)
+    with pytest.raises(pkg.WDError):          # snapshot buffer overlapping X
+        c.solve(B, X=Xs[:L], tol=1e-12, j=1, x_snap=Xs, snap_every=1)
+    c.close()
