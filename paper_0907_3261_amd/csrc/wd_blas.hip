@@ -23,6 +23,9 @@ typedef double dbl4 __attribute__((ext_vector_type(4)));
 constexpr int kWG = 256;         // threads per workgroup of the row kernels
 constexpr int kPStride = 272;    // complex entries per partial block: 16x16 tile + 16 extras
 constexpr int kMaxPartial = 512;
+// 4-row groups per wavefront and loop trip in the Gram kernels: eight keep 8 (k_gram) or
+// 32 (k_gram1) loads of each lane in flight
+constexpr int kRG = 8;
 
 struct GramAcc {
     dbl4 re, im;
@@ -99,17 +102,17 @@ __global__ void __launch_bounds__(kWG) k_gram(const double2* __restrict__ P, con
     const bool colok = col < L;
     GramAcc acc;
     gram_zero(acc);
-    for (size_t n0 = rr.r0 + 16 * w; n0 < rr.r1; n0 += 16 * (kWG / 64)) {
-        cx<double> a[4], b[4];
+    for (size_t n0 = rr.r0 + 4 * kRG * w; n0 < rr.r1; n0 += 4 * kRG * (kWG / 64)) {
+        cx<double> a[kRG], b[kRG];
 #pragma unroll
-        for (int r = 0; r < 4; ++r) {
+        for (int r = 0; r < kRG; ++r) {
             const size_t n = n0 + 4 * r + q;
             const bool ok = colok && n < rr.r1;
             a[r] = ok ? StF64::ld(P, (size_t)col * N + n) : cx<double>{0.0, 0.0};
             b[r] = ok ? StF64::ld(Q, (size_t)col * N + n) : cx<double>{0.0, 0.0};
         }
 #pragma unroll
-        for (int r = 0; r < 4; ++r) gram_step(acc, a[r], b[r]);
+        for (int r = 0; r < kRG; ++r) gram_step(acc, a[r], b[r]);
     }
     gram_store(acc, partial + (size_t)blockIdx.x * kPStride, sh);
 }
@@ -126,10 +129,10 @@ __global__ void __launch_bounds__(kWG) k_gram1(const double2* __restrict__ Rt, c
     GramAcc acc;
     gram_zero(acc);
     double twr_re = 0, twr_im = 0, tww = 0;
-    for (size_t n0 = rr.r0 + 16 * w; n0 < rr.r1; n0 += 16 * (kWG / 64)) {
-        cx<double> a[4], b[4], ww[4], rv[4];
+    for (size_t n0 = rr.r0 + 4 * kRG * w; n0 < rr.r1; n0 += 4 * kRG * (kWG / 64)) {
+        cx<double> a[kRG], b[kRG], ww[kRG], rv[kRG];
 #pragma unroll
-        for (int r = 0; r < 4; ++r) {
+        for (int r = 0; r < kRG; ++r) {
             const size_t n = n0 + 4 * r + q;
             const bool ok = colok && n < rr.r1;
             const size_t idx = (size_t)col * N + n;
@@ -139,7 +142,7 @@ __global__ void __launch_bounds__(kWG) k_gram1(const double2* __restrict__ Rt, c
             rv[r] = ok ? StF64::ld(R, idx) : cx<double>{0.0, 0.0};
         }
 #pragma unroll
-        for (int r = 0; r < 4; ++r) {
+        for (int r = 0; r < kRG; ++r) {
             gram_step(acc, a[r], b[r]);
             const cx<double> p = cmulc(ww[r], rv[r]);
             twr_re += p.re;
