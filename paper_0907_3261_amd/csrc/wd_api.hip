@@ -76,16 +76,6 @@ SmallLayout small_layout(wd_ctx* c) {
 }
 constexpr size_t kSmallPairs = 1032 + (sizeof(Ctl) + 15) / 16 + 1;
 
-int lowp_ensure(wd_ctx* c) {
-    if (c->lp[0]) return WD_OK;
-    const size_t bytes = block_elems(c, c->max_L) * sizeof(float2);
-    for (int i = 0; i < 3; ++i) {
-        int r = dev_alloc(&c->lp[i], bytes);
-        if (r != WD_OK) return r;
-    }
-    return WD_OK;
-}
-
 int check_prec(int prec) { return (prec == WD_F64 || prec == WD_F32 || prec == WD_BF16) ? WD_OK : WD_EINVAL; }
 
 // host copy of the squared column norms of an N x L block
@@ -100,6 +90,22 @@ int colnorms_host(wd_ctx* c, const double2* R, int L, double* out) {
 }
 
 }  // namespace
+
+namespace wd {
+
+// The three low-precision block buffers (FP32-sized), allocated on first use;
+// a buffer whose allocation failed earlier is tried again.
+int lowp_ensure(wd_ctx* c) {
+    const size_t bytes = block_elems(c, c->max_L) * sizeof(float2);
+    for (int i = 0; i < 3; ++i) {
+        if (c->lp[i]) continue;
+        int r = dev_alloc(&c->lp[i], bytes);
+        if (r != WD_OK) return r;
+    }
+    return WD_OK;
+}
+
+}  // namespace wd
 
 extern "C" {
 

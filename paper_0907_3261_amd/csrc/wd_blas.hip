@@ -523,8 +523,8 @@ __global__ void __launch_bounds__(kWG) k_update_PV(double2* __restrict__ P, doub
     }
 }
 
-__global__ void k_axpby(const double2* __restrict__ B, const double2* __restrict__ AX, double2* __restrict__ R,
-                        size_t n) {
+// R = B - AX elementwise; R may be AX (each element is read before it is written)
+__global__ void k_axpby(const double2* __restrict__ B, const double2* AX, double2* R, size_t n) {
     const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
     const double2 b = B[i], a = AX[i];

@@ -330,6 +330,7 @@ hipError_t launch_hop_repeat_lowp(wd_ctx* c, const double2* X, const double2* R,
 hipError_t launch_learned(wd_ctx* c, const double2* R, double2* Z, int L, Prec p, double2* t0, double2* t1,
                           hipStream_t s);
 int learned_ensure(wd_ctx* c);
+int lowp_ensure(wd_ctx* c);  // allocates the three low-precision block buffers
 
 // ---- block kernels (wd_blas.hip)
 size_t partial_stride();  // complex entries per partial block

@@ -383,12 +383,9 @@ int learn_ws(wd_ctx* c, LearnWs& w) {
         }
         c->learn_bytes = bytes;
     }
-    if (!c->lp[0]) {
-        for (int i = 0; i < 3; ++i)
-            if (hipMalloc(&c->lp[i], blk * sizeof(float2)) != hipSuccess) {
-                (void)hipGetLastError();
-                return WD_ENOMEM;
-            }
+    {
+        const int r = lowp_ensure(c);
+        if (r != WD_OK) return r;
     }
     char* p = (char*)c->learn_mem;
     w.z[0] = (float2*)c->lp[0];
