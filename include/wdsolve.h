@@ -138,6 +138,7 @@ typedef struct wd_solve_info {
  * Lz, Lt, each >= 2) with up to max_L right-hand sides (1..WD_MAX_L).
  * bc_t: 0 periodic, 1 antiperiodic in t.  hip_stream: a hipStream_t (NULL
  * for the default stream).  Workspace for max_L columns is allocated here.
+ * The volume may not exceed 2^28 sites.
  * Errors: WD_EINVAL, WD_ENOMEM, WD_EHIP. */
 int wd_create(wd_ctx** out, const int dims[4], int bc_t, int max_L, void* hip_stream);
 

@@ -157,7 +157,9 @@ int wd_create(wd_ctx** out, const int dims[4], int bc_t, int max_L, void* hip_st
     if (bc_t != 0 && bc_t != 1) return WD_EINVAL;
     if (max_L < 1 || max_L > WD_MAX_L) return WD_EINVAL;
     const long long V = (long long)dims[0] * dims[1] * dims[2] * dims[3];
-    if (V > (1LL << 31) - 1) return WD_EINVAL;  // site indices are 32-bit
+    // site indices are 32-bit, and the stencil kernels address a field plane with 32-bit
+    // byte offsets (16 bytes per site in FP64)
+    if (V > (1LL << 28)) return WD_EINVAL;
     wd_ctx* c = new (std::nothrow) wd_ctx();
     if (!c) return WD_ENOMEM;
     c->g.lx = dims[0];
