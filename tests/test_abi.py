@@ -50,6 +50,27 @@ def test_strerror_without_gpu(lib):
     assert "breakdown" in pkg.strerror(2)
 
 
+def test_argument_checks_without_gpu(lib):
+    """Entry points reject bad arguments before any HIP call, so this runs on the CPU."""
+    import ctypes
+    from ctypes import c_int, c_void_p
+    import paper_0907_3261_amd as pkg
+    L = pkg.load()                                    # argument and result types set from the header table
+    h = c_void_p()
+
+    def create(dims, bc_t=0, max_L=4):
+        return L.wd_create(ctypes.byref(h), (c_int * 4)(*dims), bc_t, max_L, None)
+
+    assert create((4, 4, 1, 4)) == -1                 # extent below 2
+    assert create((4, 4, 4, 4), bc_t=2) == -1         # boundary flag
+    assert create((4, 4, 4, 4), max_L=0) == -1
+    assert create((4, 4, 4, 4), max_L=pkg.WD_MAX_L + 1) == -1
+    assert create((1024, 1024, 512, 2)) == -1          # 2^29 sites: above the 2^28 limit
+    assert not h.value
+    assert L.wd_create(None, (c_int * 4)(4, 4, 4, 4), 0, 4, None) == -1
+    assert L.wd_destroy(None) == -1
+
+
 def test_struct_layouts_match_header():
     """Field order and sizes of the option/info structs mirror the C declarations."""
     import ctypes
