@@ -574,17 +574,21 @@ int bbicggr_solve(wd_ctx* c, const void* Bv, void* Xv, int L, double tol, const 
         }
         if (res <= tol) run_status = WD_OK;
         for (int k = 0; run_status == WD_NOT_CONVERGED && k < max_iter; ++k) {
-            // alpha and zeta
-            WD_TRY_HIP(launch_gram1(Rt, V, W, R, N, L, c->partial, S.nb, st));
+            // alpha and zeta; after the first iteration the P / V update of the previous one
+            // has already left Rt^H V, Tr[W^H R] and Tr[W^H W] in the partial blocks
+            if (k == 0) {
+                WD_TRY_HIP(launch_gram1(Rt, V, W, R, N, L, c->partial, S.nb, st));
+                S.blocks(4);
+            }
             WD_TRY_HIP(launch_solve_alpha(c->partial, S.nb, L, S.bufs, st));
             // U = (P - zeta V) alpha ; G = M U ; Y = A G
             WD_TRY_HIP(launch_update_U(P, V, S.sl.zeta, S.sl.alpha, U, N, L, st));
-            S.blocks(4 + 3 + 11);
+            S.blocks(3 + 9);  // U; X, R update with Rt^H R_{k+1} and the norms
             const long long mp = S.mvm_paper, ma = S.mvm_actual;
             if ((r = S.applyM(U, G))) return r;
             if ((r = S.applyA(G, Y))) return r;
             // X += zeta F + G ; R -= zeta W + Y ; Rt^H R_{k+1}, norms ; gamma
-            WD_TRY_HIP(launch_update_XR(X, R, F, G, W, Y, Rt, S.sl.zeta, N, L, c->partial, S.nb, st));
+            WD_TRY_HIP(launch_update_XR_gram(X, R, F, G, W, Y, Rt, S.sl.zeta, N, L, c->partial, S.nb, st));
             WD_TRY_HIP(launch_solve_gamma(c->partial, S.nb, L, S.bufs, st));
             if ((r = S.fetch_ctl(hc))) return r;
             if (hc->status & 1) {  // alpha system singular: X and R were left unchanged
@@ -642,9 +646,9 @@ int bbicggr_solve(wd_ctx* c, const void* Bv, void* Xv, int L, double tol, const 
                 run_status = WD_BREAKDOWN;
                 break;
             }
-            // P = R + U gamma ; V = W + Y gamma
-            WD_TRY_HIP(launch_update_PV(P, V, R, W, U, Y, S.sl.gamma, N, L, st));
-            S.blocks(6);
+            // P = R + U gamma ; V = W + Y gamma, with the next iteration's Gram products
+            WD_TRY_HIP(launch_update_PV_gram(P, V, R, W, U, Y, S.sl.gamma, Rt, N, L, c->partial, S.nb, st));
+            S.blocks(7);
         }
         total_iters += iters;
         // an inexact M whose cycle stalled, blew up or broke down.  Unless the caller turned the

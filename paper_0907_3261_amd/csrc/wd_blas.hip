@@ -430,6 +430,160 @@ __global__ void __launch_bounds__(kRT) k_solve_gamma(const double2* __restrict__
 // ---------------------------------------------------------------------------
 // Row-wise L x L right multiplications (one thread per row, L compile-time)
 // ---------------------------------------------------------------------------
+// The Gram tile Rt^H S over the kWG rows [c0, c0 + kWG) of one chunk, where S
+// is staged in LDS as sS[col][row - c0] by the update above it: each wave takes
+// 64 rows, lane (col = lane % 16, q = lane / 16) feeds rows 4 r + q.
+template <int L>
+__device__ __forceinline__ void gram_chunk(GramAcc& acc, const double2* __restrict__ Rt, const double2 (*sS)[kWG + 1],
+                                           size_t N, size_t c0, size_t r1) {
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const int col = lane & 15, q = lane >> 4;
+#pragma unroll
+    for (int r = 0; r < 16; ++r) {
+        const int rl = 64 * w + 4 * r + q;
+        const size_t n = c0 + rl;
+        const bool ok = col < L && n < r1;
+        const cx<double> a = ok ? StF64::ld(Rt, (size_t)col * N + n) : cx<double>{0.0, 0.0};
+        cx<double> b = {0.0, 0.0};
+        if (ok) b = {sS[col][rl].x, sS[col][rl].y};
+        gram_step(acc, a, b);
+    }
+}
+
+// P = R + U gamma, V = W + Y gamma (Sec. 2, the last two updates of an
+// iteration), fused with the Gram products that open the next iteration:
+// Rt^H V (tile), Tr[W^H R] (extra 0) and Tr[W^H W] (extra 1), written to the
+// partial blocks as k_gram1 writes them.
+template <int L>
+__global__ void __launch_bounds__(kWG) k_update_PV_gram(double2* __restrict__ P, double2* __restrict__ V,
+                                                        const double2* __restrict__ R, const double2* __restrict__ W,
+                                                        const double2* __restrict__ U, const double2* __restrict__ Y,
+                                                        const double2* __restrict__ gamma,
+                                                        const double2* __restrict__ Rt, size_t N,
+                                                        double2* __restrict__ partial, int nb) {
+    __shared__ double2 sS[L][kWG + 1];
+    __shared__ double2 sh[kWG / 64 * 256];
+    const RowRange rr = block_rows(N, nb);
+    GramAcc acc;
+    gram_zero(acc);
+    double twr_re = 0, twr_im = 0, tww = 0;
+    for (size_t c0 = rr.r0; c0 < rr.r1; c0 += kWG) {
+        const size_t n = c0 + threadIdx.x;
+        if (n < rr.r1) {
+            cx<double> u[L], y[L];
+#pragma unroll
+            for (int i = 0; i < L; ++i) {
+                u[i] = StF64::ld(U, (size_t)i * N + n);
+                y[i] = StF64::ld(Y, (size_t)i * N + n);
+            }
+#pragma unroll
+            for (int j = 0; j < L; ++j) {
+                cx<double> p = StF64::ld(R, (size_t)j * N + n);
+                cx<double> v = StF64::ld(W, (size_t)j * N + n);
+                const cx<double> wr = cmulc(v, p);
+                twr_re += wr.re;
+                twr_im += wr.im;
+                tww += v.re * v.re + v.im * v.im;
+#pragma unroll
+                for (int i = 0; i < L; ++i) {
+                    const cx<double> gm = StF64::ld(gamma, i * L + j);
+                    cfma(p, u[i], gm);
+                    cfma(v, y[i], gm);
+                }
+                StF64::st(P, (size_t)j * N + n, p);
+                StF64::st(V, (size_t)j * N + n, v);
+                sS[j][threadIdx.x] = make_double2(v.re, v.im);
+            }
+        }
+        __syncthreads();
+        gram_chunk<L>(acc, Rt, sS, N, c0, rr.r1);
+        __syncthreads();
+    }
+    double2* out = partial + (size_t)blockIdx.x * kPStride;
+    gram_store(acc, out, sh);
+    __syncthreads();
+    double* shd = reinterpret_cast<double*>(sh);
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    twr_re = wave_sum(twr_re);
+    twr_im = wave_sum(twr_im);
+    tww = wave_sum(tww);
+    if (lane == 0) {
+        shd[w * 3 + 0] = twr_re;
+        shd[w * 3 + 1] = twr_im;
+        shd[w * 3 + 2] = tww;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double a0 = 0, a1 = 0, a2 = 0;
+        for (int q2 = 0; q2 < kWG / 64; ++q2) {
+            a0 += shd[q2 * 3 + 0];
+            a1 += shd[q2 * 3 + 1];
+            a2 += shd[q2 * 3 + 2];
+        }
+        out[256] = make_double2(a0, a1);
+        out[257] = make_double2(a2, 0.0);
+    }
+}
+
+// X += zeta F + G, R -= zeta W + Y (Sec. 2), fused with the products the
+// gamma system needs: the squared column norms of R_{k+1} (extras 0..L-1)
+// and Rt^H R_{k+1} (tile).
+template <int L>
+__global__ void __launch_bounds__(kWG) k_update_XR_gram(double2* __restrict__ X, double2* __restrict__ R,
+                                                        const double2* __restrict__ F, const double2* __restrict__ G,
+                                                        const double2* __restrict__ W, const double2* __restrict__ Y,
+                                                        const double2* __restrict__ zp,
+                                                        const double2* __restrict__ Rt, size_t N,
+                                                        double2* __restrict__ partial, int nb) {
+    __shared__ double2 sS[L][kWG + 1];
+    __shared__ double2 sh[kWG / 64 * 256];
+    const RowRange rr = block_rows(N, nb);
+    const cx<double> z = StF64::ld(zp, 0);
+    GramAcc acc;
+    gram_zero(acc);
+    double nrm[L];
+#pragma unroll
+    for (int i = 0; i < L; ++i) nrm[i] = 0.0;
+    for (size_t c0 = rr.r0; c0 < rr.r1; c0 += kWG) {
+        const size_t n = c0 + threadIdx.x;
+        if (n < rr.r1) {
+#pragma unroll
+            for (int i = 0; i < L; ++i) {
+                const size_t idx = (size_t)i * N + n;
+                cx<double> x = StF64::ld(X, idx);
+                cfma(x, z, StF64::ld(F, idx));
+                x = x + StF64::ld(G, idx);
+                StF64::st(X, idx, x);
+                cx<double> rn = StF64::ld(R, idx) - StF64::ld(Y, idx);
+                cfma(rn, -z, StF64::ld(W, idx));
+                StF64::st(R, idx, rn);
+                nrm[i] += rn.re * rn.re + rn.im * rn.im;
+                sS[i][threadIdx.x] = make_double2(rn.re, rn.im);
+            }
+        }
+        __syncthreads();
+        gram_chunk<L>(acc, Rt, sS, N, c0, rr.r1);
+        __syncthreads();
+    }
+    double2* out = partial + (size_t)blockIdx.x * kPStride;
+    gram_store(acc, out, sh);
+    __syncthreads();
+    double* shd = reinterpret_cast<double*>(sh);
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+#pragma unroll
+    for (int i = 0; i < L; ++i) {
+        const double v = wave_sum(nrm[i]);
+        if (lane == 0) shd[w * 16 + i] = v;
+    }
+    __syncthreads();
+    if (threadIdx.x < 16) {
+        double sum = 0.0;
+        if ((int)threadIdx.x < L)
+            for (int q2 = 0; q2 < kWG / 64; ++q2) sum += shd[q2 * 16 + threadIdx.x];
+        out[256 + threadIdx.x] = make_double2(sum, 0.0);
+    }
+}
+
 template <int L>
 __global__ void __launch_bounds__(kWG) k_update_U(const double2* __restrict__ P, const double2* __restrict__ V,
                                                   const double2* __restrict__ zp, const double2* __restrict__ alpha,
@@ -454,75 +608,6 @@ __global__ void __launch_bounds__(kWG) k_update_U(const double2* __restrict__ P,
 
 // X += zeta F + G ; R <- R - zeta W - Y ; per-column ||R||^2 into the partial
 // extras (one thread per row, L columns; coalesced across the wavefront).
-template <int L>
-__global__ void __launch_bounds__(kWG) k_update_XR_rows(double2* __restrict__ X, double2* __restrict__ R,
-                                                        const double2* __restrict__ F, const double2* __restrict__ G,
-                                                        const double2* __restrict__ W, const double2* __restrict__ Y,
-                                                        const double2* __restrict__ zp, size_t N,
-                                                        double2* __restrict__ partial, int nb) {
-    __shared__ double shd[kWG / 64 * 16];
-    const RowRange rr = block_rows(N, nb);
-    const cx<double> z = StF64::ld(zp, 0);
-    double nrm[L];
-#pragma unroll
-    for (int i = 0; i < L; ++i) nrm[i] = 0.0;
-    for (size_t n = rr.r0 + threadIdx.x; n < rr.r1; n += kWG) {
-#pragma unroll
-        for (int i = 0; i < L; ++i) {
-            const size_t idx = (size_t)i * N + n;
-            cx<double> x = StF64::ld(X, idx);
-            cfma(x, z, StF64::ld(F, idx));
-            x = x + StF64::ld(G, idx);
-            StF64::st(X, idx, x);
-            cx<double> rn = StF64::ld(R, idx) - StF64::ld(Y, idx);
-            cfma(rn, -z, StF64::ld(W, idx));
-            StF64::st(R, idx, rn);
-            nrm[i] += rn.re * rn.re + rn.im * rn.im;
-        }
-    }
-    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-#pragma unroll
-    for (int i = 0; i < L; ++i) {
-        const double v = wave_sum(nrm[i]);
-        if (lane == 0) shd[w * 16 + i] = v;
-    }
-    __syncthreads();
-    if (threadIdx.x < 16) {
-        double sum = 0.0;
-        if ((int)threadIdx.x < L)
-            for (int q = 0; q < kWG / 64; ++q) sum += shd[q * 16 + threadIdx.x];
-        partial[(size_t)blockIdx.x * kPStride + 256 + threadIdx.x] = make_double2(sum, 0.0);
-    }
-}
-
-template <int L>
-__global__ void __launch_bounds__(kWG) k_update_PV(double2* __restrict__ P, double2* __restrict__ V,
-                                                   const double2* __restrict__ R, const double2* __restrict__ W,
-                                                   const double2* __restrict__ U, const double2* __restrict__ Y,
-                                                   const double2* __restrict__ gamma, size_t N) {
-    const size_t n = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (n >= N) return;
-    cx<double> u[L], y[L];
-#pragma unroll
-    for (int i = 0; i < L; ++i) {
-        u[i] = StF64::ld(U, (size_t)i * N + n);
-        y[i] = StF64::ld(Y, (size_t)i * N + n);
-    }
-#pragma unroll
-    for (int j = 0; j < L; ++j) {
-        cx<double> p = StF64::ld(R, (size_t)j * N + n);
-        cx<double> v = StF64::ld(W, (size_t)j * N + n);
-#pragma unroll
-        for (int i = 0; i < L; ++i) {
-            const cx<double> gm = StF64::ld(gamma, i * L + j);
-            cfma(p, u[i], gm);
-            cfma(v, y[i], gm);
-        }
-        StF64::st(P, (size_t)j * N + n, p);
-        StF64::st(V, (size_t)j * N + n, v);
-    }
-}
-
 // R = B - AX elementwise; R may be AX (each element is read before it is written)
 __global__ void k_axpby(const double2* __restrict__ B, const double2* AX, double2* R, size_t n) {
     const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -615,24 +700,21 @@ hipError_t launch_update_U(const double2* P, const double2* V, const double2* ze
     return hipGetLastError();
 }
 
-hipError_t launch_update_PV(double2* P, double2* V, const double2* R, const double2* W, const double2* U,
-                            const double2* Y, const double2* gamma, size_t N, int L, hipStream_t s) {
-#define WD_CALL_PV(l) k_update_PV<l><<<nblk(N, kWG), kWG, 0, s>>>(P, V, R, W, U, Y, gamma, N)
-    WD_L_SWITCH(L, WD_CALL_PV)
-#undef WD_CALL_PV
+hipError_t launch_update_PV_gram(double2* P, double2* V, const double2* R, const double2* W, const double2* U,
+                                 const double2* Y, const double2* gamma, const double2* Rt, size_t N, int L,
+                                 double2* partial, int nb, hipStream_t s) {
+#define WD_CALL_PVG(l) k_update_PV_gram<l><<<nb, kWG, 0, s>>>(P, V, R, W, U, Y, gamma, Rt, N, partial, nb)
+    WD_L_SWITCH(L, WD_CALL_PVG)
+#undef WD_CALL_PVG
     return hipGetLastError();
 }
 
-hipError_t launch_update_XR(double2* X, double2* R, const double2* F, const double2* G, const double2* W,
-                            const double2* Y, const double2* Rt, const double2* zeta, size_t N, int L,
-                            double2* partial, int nb, hipStream_t s) {
-    // the update writes the norm extras, the Gram kernel the tile of the same partial blocks
-#define WD_CALL_XR(l) k_update_XR_rows<l><<<nb, kWG, 0, s>>>(X, R, F, G, W, Y, zeta, N, partial, nb)
-    WD_L_SWITCH(L, WD_CALL_XR)
-#undef WD_CALL_XR
-    hipError_t e = hipGetLastError();
-    if (e != hipSuccess) return e;
-    k_gram<<<nb, kWG, 0, s>>>(Rt, R, N, L, partial, nb);
+hipError_t launch_update_XR_gram(double2* X, double2* R, const double2* F, const double2* G, const double2* W,
+                                 const double2* Y, const double2* Rt, const double2* zeta, size_t N, int L,
+                                 double2* partial, int nb, hipStream_t s) {
+#define WD_CALL_XRG(l) k_update_XR_gram<l><<<nb, kWG, 0, s>>>(X, R, F, G, W, Y, zeta, Rt, N, partial, nb)
+    WD_L_SWITCH(L, WD_CALL_XRG)
+#undef WD_CALL_XRG
     return hipGetLastError();
 }
 

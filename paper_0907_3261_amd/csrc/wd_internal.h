@@ -357,12 +357,13 @@ hipError_t launch_gram1(const double2* Rt, const double2* V, const double2* W, c
 hipError_t launch_solve_alpha(const double2* partial, int nb, int L, const SolverBufs& b, hipStream_t s);
 hipError_t launch_update_U(const double2* P, const double2* V, const double2* zeta, const double2* alpha,
                            double2* U, size_t N, int L, hipStream_t s);
-hipError_t launch_update_XR(double2* X, double2* R, const double2* F, const double2* G, const double2* W,
-                            const double2* Y, const double2* Rt, const double2* zeta, size_t N, int L,
-                            double2* partial, int nb, hipStream_t s);
 hipError_t launch_solve_gamma(const double2* partial, int nb, int L, const SolverBufs& b, hipStream_t s);
-hipError_t launch_update_PV(double2* P, double2* V, const double2* R, const double2* W, const double2* U,
-                            const double2* Y, const double2* gamma, size_t N, int L, hipStream_t s);
+hipError_t launch_update_PV_gram(double2* P, double2* V, const double2* R, const double2* W, const double2* U,
+                                 const double2* Y, const double2* gamma, const double2* Rt, size_t N, int L,
+                                 double2* partial, int nb, hipStream_t s);
+hipError_t launch_update_XR_gram(double2* X, double2* R, const double2* F, const double2* G, const double2* W,
+                                 const double2* Y, const double2* Rt, const double2* zeta, size_t N, int L,
+                                 double2* partial, int nb, hipStream_t s);
 // residual helpers
 hipError_t launch_axpby_block(const double2* B, const double2* AX, double2* R, size_t n, hipStream_t s);  // R = B - AX
 hipError_t launch_colnorms(const double2* R, size_t N, int L, double2* partial, int nb, double* norms,
