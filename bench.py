@@ -349,6 +349,10 @@ def main():
                     ctx.learned_init("neumann")
                     th = {"neumann3": ctx.get_learned()}
                 leg.update(learned_solves(ctx, torch, np, B, L, w, a, th, Xref))
+            ref = leg.get(f"jacobi{a.j}_f64", {}).get("s_per_rhs")
+            for rec in leg.values():     # time-to-solution ratio against the plain FP64 Jacobi form
+                if ref and rec.get("status") == "converged":
+                    rec["speedup_vs_f64_jacobi"] = round(ref / rec["s_per_rhs"], 3)
             solves[f"kappa{kp}"] = leg
         ctx.set_params(kappa, w["csw"])
 
