@@ -276,13 +276,15 @@ def main():
     if a.kernels_only:
         ms_sweep = time_hop(ctx, torch, V, L, 1, a.hop_reps)
         ms_apply = time_hop(ctx, torch, V, L, 0, a.hop_reps)
+        ms_lowp = {p: time_hop(ctx, torch, V, L, 1, a.hop_reps, p) for p in ("f32", "bf16")}
         X = torch.empty((L, 12, V), dtype=torch.complex128, device="cuda")
         Y = torch.empty_like(X)
         X.fill_(1.0)
         for _ in range(3):
             Y.copy_(X)
         torch.cuda.synchronize()
-        print(json.dumps({"sweep_ms": ms_sweep, "apply_ms": ms_apply, "copy_bytes_read": X.numel() * 16,
+        print(json.dumps({"sweep_ms": ms_sweep, "apply_ms": ms_apply, "sweep_lowp_ms": ms_lowp,
+                          "copy_bytes_read": X.numel() * 16,
                           "src_hash": src_hash()}), flush=True)
         ctx.close()
         return
