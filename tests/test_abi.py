@@ -71,6 +71,34 @@ def test_argument_checks_without_gpu(lib):
     assert L.wd_destroy(None) == -1
 
 
+def test_header_is_plain_c99_and_links(tmp_path, lib):
+    """The ABI header compiles as strict C99, and a C program links against the library
+    and gets WD_EINVAL for a bad extent without touching the GPU."""
+    import shutil
+    import subprocess
+    if shutil.which("gcc") is None:
+        pytest.skip("gcc not available")
+    src = tmp_path / "abi.c"
+    src.write_text(
+        '#include <stdio.h>\n#include "wdsolve.h"\n'
+        "int main(void) {\n"
+        "    wd_ctx* c = 0;\n"
+        "    const int dims[4] = {4, 4, 1, 4};\n"
+        "    int r = wd_create(&c, dims, 0, 4, 0);\n"
+        '    printf("%d %s\\n", r, wd_strerror(r));\n'
+        "    return (r == WD_EINVAL && c == 0) ? 0 : 1;\n"
+        "}\n")
+    import paper_0907_3261_amd as pkg
+    exe = tmp_path / "abi"
+    libdir = os.path.dirname(pkg.LIB_PATH)
+    cmd = ["gcc", "-std=c99", "-Wall", "-Wextra", "-Werror", "-pedantic", "-I", os.path.dirname(HEADER), str(src),
+           "-o", str(exe), "-L", libdir, "-lwdsolve", "-Wl,-rpath," + libdir]
+    subprocess.run(cmd, check=True, capture_output=True)
+    out = subprocess.run([str(exe)], capture_output=True, text=True, timeout=120)
+    assert out.returncode == 0, out.stdout + out.stderr
+    assert "invalid argument" in out.stdout
+
+
 def test_struct_layouts_match_header():
     """Field order and sizes of the option/info structs mirror the C declarations."""
     import ctypes
