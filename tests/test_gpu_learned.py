@@ -109,6 +109,30 @@ def test_gradient_matches_oracle(pkg, L):
     c.close()
 
 
+def test_adam_steps_match_oracle(pkg):
+    """Three Adam steps on the GPU (FP32 network, FP64 moments) against the oracle's Adam on
+    the same batch.  Each step moves a weight by about lr = 1e-3 in its gradient's sign; the
+    FP32 gradient of the smallest components (|g| ~ 2e-3 against a largest 12) can differ by
+    a few per cent, which changes Adam's normalised step by as much, so the weights must agree
+    to 1e-4 (3 % of the 3e-3 they move).  A wrong lr, beta, bias correction or sign is off by
+    at least 1e-3."""
+    dims = (4, 4, 2, 4)
+    c, op = _ctx(pkg, dims)
+    th0 = _theta(3, 0.2)
+    c.set_learned(th0)
+    L = 2
+    R = wi.gaussian_block(op.V, L, 411)
+    E = wi.gaussian_block(op.V, L, 412)
+    hist = c.learned_train(torch.from_numpy(R).cuda(), torch.from_numpy(E).cuda(), L, steps=3, lr=1e-3)
+    th_gpu = c.get_learned().astype(np.complex128)
+    th_o, hist_o = ln.train(op, th0, op.from_block(R), op.from_block(E), 3, L, lr=1e-3)
+    _say(f"adam: max |dtheta| {np.max(np.abs(th_gpu - th_o)):.2e}, loss {hist} vs {np.array(hist_o)}")
+    np.testing.assert_allclose(hist, hist_o, rtol=1e-5)
+    assert np.max(np.abs(th_gpu - th_o)) < 1e-4
+    assert np.max(np.abs(th_gpu - th0)) > 2e-3          # the weights did move (about 3 lr)
+    c.close()
+
+
 def _neumann_theta(kappa):
     """The factored series (1 + x)(1 + i x)(1 - i x), x = kappa H, built from the oracle's gammas."""
     g = gammas()
