@@ -138,7 +138,7 @@ __device__ __forceinline__ void hop_dir(cx<R> (&acc)[12], const cx<R> (&u)[9], c
 // once and applied to every column.  Xc is the wave-uniform base of the
 // thread's first column; link_off and nb_off are byte offsets of the link's
 // site and of the neighbour site inside one plane.
-template <class S, int MU, bool FWD, bool ADD, int CT, bool NT = false, bool NTU = false>
+template <class S, int MU, bool FWD, bool ADD, int CT, bool NT = false>
 __device__ __forceinline__ void hop_all(cx<typename S::R> (&acc)[CT][12], const typename S::P* __restrict__ Uk,
                                         const typename S::P* __restrict__ Xc, uint32_t link_off, uint32_t nb_off,
                                         size_t V) {
@@ -148,8 +148,7 @@ __device__ __forceinline__ void hop_all(cx<typename S::R> (&acc)[CT][12], const 
     __builtin_amdgcn_sched_barrier(0);
     cx<R> u[9];
 #pragma unroll
-    for (int k = 0; k < 9; ++k)
-        u[k] = NTU ? S::ldb_nt(Uk + (size_t)(MU * 9 + k) * V, link_off) : S::ldb(Uk + (size_t)(MU * 9 + k) * V, link_off);
+    for (int k = 0; k < 9; ++k) u[k] = S::ldb(Uk + (size_t)(MU * 9 + k) * V, link_off);
 #pragma unroll
     for (int c = 0; c < CT; ++c) {
         cx<R> p[12];
@@ -240,8 +239,8 @@ __global__ void __launch_bounds__(256)
     hop_all<SF, 1, false, ADD, CT>(acc, Uk, Xc, o_by, o_by, V);
     hop_all<SF, 2, true, ADD, CT>(acc, Uk, Xc, o_s, o_fz, V);
     hop_all<SF, 2, false, ADD, CT>(acc, Uk, Xc, o_bz, o_bz, V);
-    hop_all<SF, 3, true, ADD, CT, (NTP & 2) != 0, (NTP & 8) != 0>(acc, Uk, Xc, o_s, o_ft, V);
-    hop_all<SF, 3, false, ADD, CT, (NTP & 2) != 0, (NTP & 8) != 0>(acc, Uk, Xc, o_bt, o_bt, V);
+    hop_all<SF, 3, true, ADD, CT, (NTP & 2) != 0>(acc, Uk, Xc, o_s, o_ft, V);
+    hop_all<SF, 3, false, ADD, CT, (NTP & 2) != 0>(acc, Uk, Xc, o_bt, o_bt, V);
     __builtin_amdgcn_sched_barrier(0);
 
     PY* Yc = Y + (size_t)c0 * cs;
@@ -351,7 +350,7 @@ int hop_ntp() {
     static int v = [] {
         const char* e = std::getenv("WDSOLVE_HOP_NT");
         const int x = e ? std::atoi(e) : 2;
-        return ((x >= 0 && x <= 3) || x == 10) ? x : 2;
+        return (x >= 0 && x <= 3) ? x : 2;
     }();
     return v;
 }
@@ -391,9 +390,6 @@ hipError_t launch_hop_ct(const Geom& g, const void* Uk, const void* Cl, const vo
         else if (ntp == 3)
             k_hop<SF, SY, CT, MODE, 3><<<grid, block, 0, s>>>(g, sm, (const PF*)Uk, (const PF*)Cl, (const PF*)X,
                                                               (const PF*)Rh, (PY*)Y, col_begin, ntiles);
-        else if (ntp == 10)
-            k_hop<SF, SY, CT, MODE, 10><<<grid, block, 0, s>>>(g, sm, (const PF*)Uk, (const PF*)Cl, (const PF*)X,
-                                                               (const PF*)Rh, (PY*)Y, col_begin, ntiles);
         else
             k_hop<SF, SY, CT, MODE, 2><<<grid, block, 0, s>>>(g, sm, (const PF*)Uk, (const PF*)Cl, (const PF*)X,
                                                               (const PF*)Rh, (PY*)Y, col_begin, ntiles);
