@@ -50,6 +50,8 @@ def parse():
     p.add_argument("--learn-steps", type=int, default=20)
     p.add_argument("--learn-snaps", type=int, default=3, help="solver snapshots used as training pairs")
     p.add_argument("--snap-every", type=int, default=15)
+    p.add_argument("--j-sweep", action="store_true",
+                   help="only the Jacobi-step sweep: FP64 solves for j in 0, 4, 8, 12, 16, 24 at kappa and kappa-heavy")
     p.add_argument("--kappa-heavy", type=float, default=0.12,
                    help="second kappa (heavier quark) for the time-to-solution comparison; 0 skips it")
     p.add_argument("--no-cpu-baseline", action="store_true")
@@ -273,6 +275,20 @@ def main():
           file=sys.stderr, flush=True)
 
     st = ctx.stream
+    if a.j_sweep:
+        out = {}
+        for kp in [kappa] + ([a.kappa_heavy] if a.kappa_heavy > 0 else []):
+            ctx.set_params(kp, w["csw"])
+            for j in (0, 4, 8, 12, 16, 24):
+                X, info = ctx.solve(B, tol=w["tol"], j=j, max_iter=3000)
+                out[f"kappa{kp}_j{j}"] = {"status": info["status"], "iterations": info["iterations"],
+                                          "mvm_paper_per_col": int(info["mvm_paper"]),
+                                          "s_per_rhs": round(info["seconds"] / L, 5),
+                                          "true_residual_max": float(np.max(info["true_residual"]))}
+                print(f"[bench] j-sweep kappa={kp} j={j}: {out[f'kappa{kp}_j{j}']}", file=sys.stderr, flush=True)
+        print(json.dumps({"j_sweep": out, "workload": a.workload, "L": L}), flush=True)
+        ctx.close()
+        return
     if a.kernels_only:
         ms_sweep = time_hop(ctx, torch, V, L, 1, a.hop_reps)
         ms_apply = time_hop(ctx, torch, V, L, 0, a.hop_reps)
