@@ -48,8 +48,13 @@ def parse():
     p.add_argument("--no-learned", action="store_true", help="skip the learned-preconditioner leg")
     p.add_argument("--learn-pairs", type=int, default=24)
     p.add_argument("--learn-steps", type=int, default=20)
-    p.add_argument("--learn-snaps", type=int, default=3, help="solver snapshots used as training pairs")
+    p.add_argument("--learn-snaps", type=int, default=3, help="solver snapshots per logging solve")
     p.add_argument("--snap-every", type=int, default=15)
+    p.add_argument("--learn-solves", type=int, default=1,
+                   help="solves that log snapshots: the first with the workload's sources, the rest with Z4 noise")
+    p.add_argument("--learn-solver-pairs", type=int, default=0, help="cap on the solver pairs kept (0: all)")
+    p.add_argument("--learn-lr", type=float, default=1e-3)
+    p.add_argument("--learn-prec", default="f64", help="precisions of the solves with trained weights (f64,f32)")
     p.add_argument("--j-sweep", action="store_true",
                    help="only the Jacobi-step sweep: FP64 solves for j in 0, 4, 8, 12, 16, 24 at kappa and kappa-heavy")
     p.add_argument("--kappa-heavy", type=float, default=0.12,
@@ -142,30 +147,42 @@ def compare_leg(ctx, torch, np, B, L, w, a):
 def learned_setup(ctx, torch, np, B, V, L, w, a):
     """Learned preconditioner: start from the factored degree-3 Neumann series, time one
     application of M in FP64 and FP32, then train with Adam on pairs that the solver generates
-    (snapshots X_k of an FP64 Jacobi solve: r = B - A X_k, e = X - X_k) together with pairs
+    (snapshots X_k of FP64 Jacobi solves: r = B - A X_k, e = X - X_k) together with pairs
     (A e, e) for Gaussian e."""
+    import wdinputs as wi
     out = {}
     g = torch.Generator(device="cuda").manual_seed(12)
     P = a.learn_pairs - a.learn_pairs % L           # Gaussian pairs
-    S = a.learn_snaps                               # snapshot blocks of L columns
-    Ep = torch.empty(((P // L + S) * L, 12, V), dtype=torch.complex128, device="cuda")
+    S = a.learn_snaps                               # snapshot blocks of L columns per logging solve
+    K = a.learn_solves if S > 0 else 0
+    cap = K * S * L if a.learn_solver_pairs <= 0 else min(K * S * L, a.learn_solver_pairs - a.learn_solver_pairs % L)
+    Ep = torch.empty((P + cap, 12, V), dtype=torch.complex128, device="cuda")
     Rp = torch.empty_like(Ep)
     Ep[:P] = torch.complex(torch.randn((P, 12, V), generator=g, device="cuda", dtype=torch.float64),
                            torch.randn((P, 12, V), generator=g, device="cuda", dtype=torch.float64))
     for i in range(0, P, L):
         ctx.apply(Ep[i:i + L], Rp[i:i + L])
-    if S > 0:
+    n = P
+    if K > 0 and cap > 0:
         Xs = torch.empty((S * L, 12, V), dtype=torch.complex128, device="cuda")
-        X, info = ctx.solve(B, tol=w["tol"], j=a.j, x_snap=Xs, snap_every=a.snap_every)
-        ns = info["snapshots"]
-        if ns > 0:
-            r, e = ctx.learned_pairs(B, X, Xs[:ns * L])
-            Rp[P:P + ns * L] = r
-            Ep[P:P + ns * L] = e
-            del r, e
-        Rp, Ep = Rp[:P + ns * L], Ep[:P + ns * L]
-        out["solver_pairs"] = {"snapshots": ns, "every": a.snap_every, "columns": ns * L}
-        del Xs, X
+        snaps = []
+        for k in range(K):
+            Bk = B if k == 0 else torch.from_numpy(wi.source_block("z4", V, L, w["source_seed"] + 100 + k)).cuda()
+            X, info = ctx.solve(Bk, tol=w["tol"], j=a.j, x_snap=Xs, snap_every=a.snap_every)
+            ns = min(info["snapshots"], (P + cap - n) // L)
+            snaps.append(ns)
+            if ns > 0:
+                r, e = ctx.learned_pairs(Bk, X, Xs[:ns * L])
+                Rp[n:n + ns * L] = r
+                Ep[n:n + ns * L] = e
+                n += ns * L
+                del r, e
+            del X, Bk
+            if n >= P + cap:
+                break
+        out["solver_pairs"] = {"solves": len(snaps), "snapshots": snaps, "every": a.snap_every, "columns": n - P}
+        del Xs
+    Rp, Ep = Rp[:n], Ep[:n]
     ctx.learned_init("neumann")
     Z = torch.empty((L, 12, V), dtype=torch.complex128, device="cuda")
     for prec, per_layer in (("f64", 576 + 384 * L), ("f32", 288 + 192 * L)):
@@ -184,14 +201,14 @@ def learned_setup(ctx, torch, np, B, V, L, w, a):
     thetas = {"neumann3": ctx.get_learned()}
     # two trainings from the Neumann start: Gaussian pairs only, and solver pairs with them
     for name, (r, e) in (("trained_gauss", (Rp[:P], Ep[:P])), ("trained_solver", (Rp, Ep))):
-        if name == "trained_solver" and r.shape[0] == P:
+        if (name == "trained_solver" and r.shape[0] == P) or r.shape[0] == 0:
             continue
         ctx.set_learned(thetas["neumann3"])
         t0 = time.time()
-        hist = ctx.learned_train(r, e, L, steps=a.learn_steps, lr=1e-3)
+        hist = ctx.learned_train(r, e, L, steps=a.learn_steps, lr=a.learn_lr)
         torch.cuda.synchronize()
-        nb = r.shape[0] // L          # batches cycle, so compare whole passes over the pairs
-        out[name] = {"pairs": int(r.shape[0]), "steps": a.learn_steps, "lr": 1e-3,
+        nb = min(r.shape[0] // L, len(hist))  # batches cycle, so compare whole passes over the pairs
+        out[name] = {"pairs": int(r.shape[0]), "steps": a.learn_steps, "lr": a.learn_lr,
                      "seconds": round(time.time() - t0, 3),
                      "loss_first_pass": float(np.mean(hist[:nb])), "loss_last_pass": float(np.mean(hist[-nb:]))}
         thetas[name] = ctx.get_learned()
@@ -206,7 +223,8 @@ def learned_solves(ctx, torch, np, B, L, w, a, thetas, Xref):
     from paper_0907_3261_amd import WD_PRECOND_LEARNED
     out = {}
     legs = [("neumann3", thetas["neumann3"], "f64"), ("neumann3", thetas["neumann3"], "f32")]
-    legs += [(k, thetas[k], "f64") for k in ("trained_gauss", "trained_solver") if thetas.get(k) is not None]
+    legs += [(k, thetas[k], p) for k in ("trained_gauss", "trained_solver") if thetas.get(k) is not None
+             for p in a.learn_prec.split(",")]
     for name, th, prec in legs:
         if th is None:
             continue
