@@ -72,82 +72,126 @@ __device__ __forceinline__ int neighbour(const Geom& g, int s, int d) {
     return c[0] + g.lx * (c[1] + g.ly * (c[2] + g.lz * c[3]));
 }
 
+// Operands of one term W_d (U or U^dag or 1) psi(nb): the link and the CT input spinors.
+template <class R, int CT>
+struct Term {
+    cx<R> u[9];
+    cx<R> p[CT][12];
+};
+
+// Issue the loads of a term.  KIND: 0 self term, 1 forward hop (link at the site),
+// 2 backward hop (daggered link at the neighbour).
+template <int KIND, class SI, class SL, class R, int CT>
+__device__ __forceinline__ void term_load(Term<R, CT>& t, const typename SL::P* __restrict__ U, int mu, int ls,
+                                          const typename SI::P* __restrict__ Zin, size_t V, size_t col0, int nb) {
+    if (KIND != 0) {
+#pragma unroll
+        for (int k = 0; k < 9; ++k) t.u[k] = SL::ld(U, (size_t)(mu * 9 + k) * V + ls);
+    }
+#pragma unroll
+    for (int c = 0; c < CT; ++c) {
+        const typename SI::P* zc = Zin + (col0 + c) * 12 * V;
+#pragma unroll
+        for (int k = 0; k < 12; ++k) {
+            const auto v = SI::ld(zc, (size_t)k * V + nb);
+            t.p[c][k] = {(R)v.re, (R)v.im};
+        }
+    }
+}
+
+// acc += W_d (U or U^dag or 1) psi for the CT columns of a loaded term
+template <int KIND, class R, int CT>
+__device__ __forceinline__ void term_apply(const Term<R, CT>& t, const float2* __restrict__ Wd, cx<R> (&acc)[CT][12]) {
+#pragma unroll
+    for (int c = 0; c < CT; ++c) {
+        // source spin tt: q = (U or U^dag or 1) psi_tt, then acc[sp] += W[sp][tt] q
+#pragma unroll
+        for (int tt = 0; tt < 4; ++tt) {
+            cx<R> q[3];
+#pragma unroll
+            for (int a = 0; a < 3; ++a) {
+                if (KIND == 0) {
+                    q[a] = t.p[c][3 * tt + a];
+                } else {
+                    cx<R> r = {R(0), R(0)};
+#pragma unroll
+                    for (int b = 0; b < 3; ++b) {
+                        if (KIND == 1)
+                            cfma(r, t.u[a * 3 + b], t.p[c][3 * tt + b]);
+                        else
+                            cfmac(r, t.u[b * 3 + a], t.p[c][3 * tt + b]);
+                    }
+                    q[a] = r;
+                }
+            }
+#pragma unroll
+            for (int sp = 0; sp < 4; ++sp) {
+                const float2 wv = Wd[sp * 4 + tt];
+                const cx<R> w = {(R)wv.x, (R)wv.y};
+#pragma unroll
+                for (int a = 0; a < 3; ++a) cfma(acc[c][3 * sp + a], w, q[a]);
+            }
+        }
+    }
+}
+
 // One layer: thread (site, tile) accumulates CT columns, so each link and
 // weight is loaded once per tile.  SI / SO: storage of input / output, SL:
 // storage (and arithmetic precision) of the links.  W: 9 x 16 complex
-// (row-major 4 x 4 per direction), FP32.  Columns [c0 + tile*CT, + CT) of
-// the block vectors; every tile of the launch is complete.
+// (row-major 4 x 4 per direction; direction 1 + 2 mu is the forward hop,
+// 2 + 2 mu the backward one), FP32.  Columns [c0 + tile*CT, + CT) of the
+// block vectors; every tile of the launch is complete.  In FP32 the nine
+// terms are software-pipelined: the operands of the next term are in flight
+// while the current one is accumulated.
 template <class SI, class SO, class SL, int CT>
-__global__ void __launch_bounds__(256) k_layer(const Geom g, const typename SL::P* __restrict__ U,
+__global__ void __launch_bounds__(256) k_layer(const Geom g, const SiteMap sm, const typename SL::P* __restrict__ U,
                                                const float2* __restrict__ W, const typename SI::P* __restrict__ Zin,
                                                typename SO::P* __restrict__ Zout, const int c0, const int ntile) {
     using R = typename SL::R;
     const size_t V = g.V;
-    const int s = blockIdx.x * 64 + threadIdx.x;
+    const int s = map_site(g, sm, blockIdx.x, threadIdx.x);
     const int tile = blockIdx.y * blockDim.y + threadIdx.y;
-    if (s >= g.V || tile >= ntile) return;
+    if (s < 0 || tile >= ntile) return;
     const int x = s % g.lx, y = (s / g.lx) % g.ly, z = (s / g.sxy) % g.lz, t = s / g.sxyz;
     const int co[4] = {x, y, z, t};
     const int ext[4] = {g.lx, g.ly, g.lz, g.lt};
     const int str[4] = {1, g.lx, g.sxy, g.sxyz};
     const size_t col0 = (size_t)(c0 + tile * CT);
+    auto fwd_site = [&](int mu) {
+        return (co[mu] + 1 == ext[mu]) ? s - (ext[mu] - 1) * str[mu] : s + str[mu];
+    };
+    auto bwd_site = [&](int mu) { return (co[mu] == 0) ? s + (ext[mu] - 1) * str[mu] : s - str[mu]; };
     cx<R> acc[CT][12];
 #pragma unroll
     for (int c = 0; c < CT; ++c)
 #pragma unroll
         for (int k = 0; k < 12; ++k) acc[c][k] = {R(0), R(0)};
-    for (int d = 0; d < kND; ++d) {
-        int nb = s, ls = s;
-        cx<R> u[9];
-        if (d > 0) {
-            const int mu = (d - 1) >> 1;
-            const bool fwd = (d & 1) != 0;
-            int cm = co[mu], off = str[mu];
-            if (fwd) nb = (cm + 1 == ext[mu]) ? s - (ext[mu] - 1) * off : s + off;
-            else nb = (cm == 0) ? s + (ext[mu] - 1) * off : s - off;
-            ls = fwd ? s : nb;
-#pragma unroll
-            for (int k = 0; k < 9; ++k) u[k] = SL::ld(U, (size_t)(mu * 9 + k) * V + ls);
+    if constexpr (sizeof(R) == 4) {
+        // FP32: two operand sets, the next term's loads in flight during the current term
+        Term<R, CT> A, B;  // A: self and backward terms, B: forward terms
+        term_load<0, SI, SL>(A, U, 0, s, Zin, V, col0, s);
+        term_load<1, SI, SL>(B, U, 0, s, Zin, V, col0, fwd_site(0));
+        term_apply<0>(A, W, acc);
+#pragma unroll 1
+        for (int mu = 0; mu < 4; ++mu) {
+            const int bw = bwd_site(mu);
+            term_load<2, SI, SL>(A, U, mu, bw, Zin, V, col0, bw);
+            term_apply<1>(B, W + (1 + 2 * mu) * 16, acc);
+            if (mu < 3) term_load<1, SI, SL>(B, U, mu + 1, s, Zin, V, col0, fwd_site(mu + 1));
+            term_apply<2>(A, W + (2 + 2 * mu) * 16, acc);
         }
-        const float2* Wd = W + d * 16;
-        const bool fwd = (d & 1) != 0;
-#pragma unroll
-        for (int c = 0; c < CT; ++c) {
-            const typename SI::P* zc = Zin + (col0 + c) * 12 * V;
-            // source spin tt: q = (U or U^dag or 1) psi_tt, then acc[sp] += W[sp][tt] q
-#pragma unroll
-            for (int tt = 0; tt < 4; ++tt) {
-                cx<R> p[3], q[3];
-#pragma unroll
-                for (int b = 0; b < 3; ++b) {
-                    const auto v = SI::ld(zc, (size_t)(3 * tt + b) * V + nb);
-                    p[b] = {(R)v.re, (R)v.im};
-                }
-                if (d == 0) {
-#pragma unroll
-                    for (int a = 0; a < 3; ++a) q[a] = p[a];
-                } else {
-#pragma unroll
-                    for (int a = 0; a < 3; ++a) {
-                        cx<R> r = {R(0), R(0)};
-#pragma unroll
-                        for (int b = 0; b < 3; ++b) {
-                            if (fwd)
-                                cfma(r, u[a * 3 + b], p[b]);
-                            else
-                                cfmac(r, u[b * 3 + a], p[b]);
-                        }
-                        q[a] = r;
-                    }
-                }
-#pragma unroll
-                for (int sp = 0; sp < 4; ++sp) {
-                    const float2 wv = Wd[sp * 4 + tt];
-                    const cx<R> w = {(R)wv.x, (R)wv.y};
-#pragma unroll
-                    for (int a = 0; a < 3; ++a) cfma(acc[c][3 * sp + a], w, q[a]);
-                }
-            }
+    } else {
+        // FP64: one operand set (two would halve the occupancy)
+        Term<R, CT> A;
+        term_load<0, SI, SL>(A, U, 0, s, Zin, V, col0, s);
+        term_apply<0>(A, W, acc);
+#pragma unroll 1
+        for (int mu = 0; mu < 4; ++mu) {
+            term_load<1, SI, SL>(A, U, mu, s, Zin, V, col0, fwd_site(mu));
+            term_apply<1>(A, W + (1 + 2 * mu) * 16, acc);
+            const int bw = bwd_site(mu);
+            term_load<2, SI, SL>(A, U, mu, bw, Zin, V, col0, bw);
+            term_apply<2>(A, W + (2 + 2 * mu) * 16, acc);
         }
     }
 #pragma unroll
@@ -315,16 +359,18 @@ hipError_t launch_layer_ct(const wd_ctx* c, const typename SL::P* U, const float
                            int c0, int ntile, hipStream_t s) {
     if (ntile <= 0) return hipSuccess;
     const int ty = ntile < 4 ? ntile : 4;
-    dim3 block(64, ty), grid(nblk(c->g.V, 64), (ntile + ty - 1) / ty);
-    k_layer<SI, SO, SL, CT><<<grid, block, 0, s>>>(c->g, U, W, (const typename SI::P*)in, (typename SO::P*)out, c0,
-                                                   ntile);
+    // XCD-aware site order, sized for the input columns of one workgroup plus the links
+    const SiteMap sm = make_site_map(c->g, 12.0 * CT * ty * sizeof(typename SI::P) + 36.0 * sizeof(typename SL::P));
+    dim3 block(64, ty), grid(sm.nblk, (ntile + ty - 1) / ty);
+    k_layer<SI, SO, SL, CT><<<grid, block, 0, s>>>(c->g, sm, U, W, (const typename SI::P*)in, (typename SO::P*)out,
+                                                   c0, ntile);
     return hipGetLastError();
 }
 
 // One layer over L columns: tiles of CT columns, then single columns for the rest.
-// Columns per thread: WDSOLVE_LEARN_CT (1, 2 or 4) if set, else 1.  At 32^3 x 64 with twelve
-// columns one column per thread is the fastest in both precisions (the wider tiles lose
-// occupancy to their accumulators, and FP64 with four columns spills).
+// Columns per thread: WDSOLVE_LEARN_CT (1, 2 or 4) if set, else 1.  At 32^3 x 64 with
+// twelve columns one column per thread is the fastest in both precisions (the wider tiles
+// lose occupancy to their accumulators and operand sets, and spill).
 inline int layer_ct(bool f64) {
     static const int env = [] {
         const char* e = std::getenv("WDSOLVE_LEARN_CT");
