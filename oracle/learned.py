@@ -28,7 +28,7 @@ from __future__ import annotations
 
 import numpy as np
 
-from .dirac import shift
+from .dirac import dag, shift
 
 NLAYER = 3
 NDIR = 9
@@ -62,6 +62,25 @@ def layer(op, W: np.ndarray, f: np.ndarray) -> np.ndarray:
     out = np.zeros_like(f)
     for d in range(NDIR):
         out += np.einsum("st,...tal->...sal", W[d], shifted(op, f, d))
+    return out
+
+
+def layer_at(so, W: np.ndarray, s: int, get_spinor) -> np.ndarray:
+    """One layer at a single site s, from the spinors of s and its eight
+    neighbours: the same sum as ``layer`` with each term written as the
+    Kronecker product (spin weight) x (link) acting on a (12, L) spinor
+    (row 3*spin + colour).  ``so`` is a ``dirac.SiteOperator`` (links,
+    coordinates, boundary signs); ``get_spinor(site)`` returns (12, L)."""
+    c = so.coords(s)
+    out = np.kron(W[0], np.eye(3)) @ get_spinor(s)
+    for mu, d, sn, sign in so.neighbours(s):
+        if d == 1:
+            M = np.kron(W[1 + 2 * mu], so.link(mu, c))
+        else:
+            c_back = list(c)
+            c_back[mu] -= 1
+            M = np.kron(W[2 + 2 * mu], dag(so.link(mu, c_back)))
+        out = out + sign * (M @ get_spinor(sn))
     return out
 
 

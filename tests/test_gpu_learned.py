@@ -223,3 +223,50 @@ def test_solver_snapshots_and_pairs(pkg):
     with pytest.raises(pkg.WDError):          # snapshot buffer overlapping X
         c.solve(B, X=Xs[:L], tol=1e-12, j=1, x_snap=Xs, snap_every=1)
     c.close()
+
+
+@pytest.mark.parametrize("prec", ["f64", "f32"])
+def test_full_size_apply_sampled(pkg, prec):
+    """Three layers with random weights on the 32^3 x 64 lattice with twelve columns, in
+    the launch configuration of the benchmark, at sampled sites: each output site depends
+    on the input within three hops, which the site-by-site oracle layers evaluate."""
+    from oracle.dirac import SiteOperator
+    w = wi.workload("lat32x64_L12_point")
+    dims, V, L = w["dims"], wi.volume(w["dims"]), 12
+    U = wi.random_links(dims, w["eps"], w["link_seed"])
+    c = pkg.Context(dims, bc_t=w["bc_t"], max_L=L)
+    c.set_links(U)
+    c.set_params(w["kappa_solve"], w["csw"])
+    th = _theta(77)
+    c.set_learned(th)
+    g = torch.Generator(device="cuda").manual_seed(9)
+    R = torch.complex(torch.randn((L, 12, V), generator=g, device="cuda", dtype=torch.float64),
+                      torch.randn((L, 12, V), generator=g, device="cuda", dtype=torch.float64))
+    Z = c.learned_apply(R, prec=prec)
+    so = SiteOperator(dims, U, w["kappa_solve"], w["csw"], w["bc_t"])
+    rng = np.random.default_rng(31)
+    sites = sorted({0, V - 1, *rng.integers(0, V, 4).tolist()})
+    ball, front = set(sites), set(sites)
+    for _ in range(3):
+        front = {n for s in front for (_, _, n, _) in so.neighbours(s)}
+        ball |= front
+    need = sorted(ball)
+    pos = {s: i for i, s in enumerate(need)}
+    Rs = R[:, :, torch.tensor(need, device="cuda")].cpu().numpy()
+    Zs = Z[:, :, torch.tensor(sites, device="cuda")].cpu().numpy()
+    del R, Z
+    c.close()
+    memo = {}
+
+    def z(l, s):                      # output of layer l at site s, (12, L); l = -1 is the input
+        if l < 0:
+            return Rs[:, :, pos[s]].T
+        if (l, s) not in memo:
+            memo[(l, s)] = ln.layer_at(so, th[l], s, lambda t: z(l - 1, t))
+        return memo[(l, s)]
+
+    ref = np.stack([z(2, s) for s in sites])
+    got = np.stack([Zs[:, :, k].T for k in range(len(sites))])
+    err = _maxrel(got, ref)
+    _say(f"full-size apply {prec} at {len(sites)} sites ({len(need)} inputs): {err:.2e}")
+    assert err < APPLY_TOL[prec]

@@ -115,3 +115,21 @@ def test_training_lowers_loss():
     l0 = ln.loss(op, th0, R, E)
     th, hist = ln.train(op, th0, R, E, steps=40, L=4, lr=1e-2)
     assert ln.loss(op, th, R, E) < 0.8 * l0
+
+
+@pytest.mark.parametrize("bc_t", [0, 1])
+def test_site_layer_matches_field_layer(bc_t):
+    """The site-by-site layer (used for full-size spot checks) equals the field layer,
+    on every site of a lattice with an odd extent and antiperiodic or periodic time."""
+    from oracle.dirac import SiteOperator
+    rng = np.random.default_rng(11)
+    dims = (3, 2, 4, 4)
+    U = wi.random_links(dims, 0.5, 21)
+    op = WilsonClover(dims, U, 0.12, 1.0, bc_t=bc_t)
+    so = SiteOperator(dims, U, 0.12, 1.0, bc_t)
+    W = _rand_theta(rng)[1]
+    b = wi.gaussian_block(op.V, 2, 8)                       # (L, 12, V)
+    ref = op.to_block(ln.layer(op, W, op.from_block(b)))
+    for s in range(op.V):
+        got = ln.layer_at(so, W, s, lambda t: b[:, :, t].T)
+        assert np.max(np.abs(got - ref[:, :, s].T)) < 1e-14
