@@ -266,6 +266,28 @@ def test_solve_first_iterations_match_oracle(pkg, k):
     c.close()
 
 
+@pytest.mark.parametrize("L", [2, 7, 9, 13, 16])
+def test_solve_every_block_width(pkg, L):
+    """The fused update kernels are instantiated per block width: for widths the workloads do
+    not use, the first two iterations equal the oracle's and a full solve reaches 1e-12 in the
+    oracle's own true residual."""
+    dims = (4, 4, 4, 6)
+    U = wi.random_links(dims, 0.3, 122)
+    op = WilsonClover(dims, U, 0.125, 1.4, bc_t=1)
+    c = _ctx(pkg, dims, U, 0.125, 1.4, 1, max_L=16)
+    B = wi.z4_block(op.V, L, 123 + L)
+    Bm = op.block_to_mat(B)
+    from oracle.jacobi import jacobi_mat
+    X, info = c.solve(_dev(B), tol=1e-30, j=2, max_iter=2, max_restarts=0)
+    Xo, io = block_bicggr(op.A_mat, lambda m: jacobi_mat(op, m, 2), Bm, 1e-30, 2, max_iter=2)
+    assert info["iterations"] == io["iterations"] == 2
+    assert _rel(op.block_to_mat(_host(X)), Xo) < 1e-12
+    X, info = c.solve(_dev(B), tol=1e-12, j=2)
+    assert info["status"] == "converged", info
+    assert np.max(true_residual(op.A_mat, Bm, op.block_to_mat(_host(X)))) <= 1e-12
+    c.close()
+
+
 def test_solve_point_sources_jacobi_oracle_residual(pkg):
     """8^3 x 16, kappa 0.135, c_SW 1.6, twelve point sources, Jacobi j = 4, 8, 12, 16."""
     w, c, op = _workload_ctx(pkg, "lat8x16_L12_point")
