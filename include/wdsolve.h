@@ -70,6 +70,12 @@ typedef struct wd_ctx wd_ctx;
 #define WD_F64 0
 #define WD_F32 1               /* FP32 storage of links, clover and spinors, FP32 arithmetic */
 #define WD_BF16 2              /* BF16 storage, FP32 arithmetic */
+/* Jacobi preconditioner only: FP64 iterates and arithmetic with the links and
+ * A_D^{-1} stored in FP32 or BF16.  Unlike WD_F32 / WD_BF16, which round the
+ * iterates, this M is a fixed linear operator to FP64 accuracy (the Jacobi
+ * iteration of a nearby matrix), so block BiCGGR needs no Krylov cycles. */
+#define WD_F64_COEF_F32 3
+#define WD_F64_COEF_BF16 4
 
 /* preconditioner M of the solver */
 #define WD_PRECOND_NONE 0      /* M = I */
@@ -86,8 +92,9 @@ typedef struct wd_ctx wd_ctx;
 typedef struct wd_solve_opts {
     int j;                 /* Jacobi steps per application of M (>= 0); 0 means M = I */
     int precond;           /* WD_PRECOND_*; NONE forces j = 0 in the cost count */
-    int prec_inner;        /* WD_F64 / WD_F32 / WD_BF16 storage of the Jacobi preconditioner;
-                              WD_F64 / WD_F32 arithmetic of the learned one */
+    int prec_inner;        /* WD_F64 / WD_F32 / WD_BF16 / WD_F64_COEF_F32 / WD_F64_COEF_BF16
+                              storage of the Jacobi preconditioner; WD_F64 / WD_F32 arithmetic
+                              of the learned one */
     int use_x0;            /* 1: X holds the initial guess; 0: start from X = 0 */
     int max_iter;          /* outer iterations per run; <= 0 means 5000 */
     int max_restarts;      /* true-residual restarts; < 0 means 3 */
@@ -178,8 +185,10 @@ int wd_apply(wd_ctx* ctx, const void* X, void* Y, int L, int prec);
  * after the algorithm box) with initial guess G_0 = 0:
  *   Z = sum_{i=0}^{j-1} (I - A_D^{-1} A)^i A_D^{-1} R  (j >= 1),  Z = R (j = 0),
  * evaluated as j sweeps Z_{i+1} = Z_i + A_D^{-1}(R - A Z_i).  prec selects the
- * storage of links, clover and the iterates (FP64, FP32 or BF16 with FP32
- * accumulation); R and Z are FP64 device block vectors and must not overlap. */
+ * storage of links, clover and the iterates (WD_F64, or WD_F32 / WD_BF16 with
+ * FP32 accumulation), or FP64 iterates with FP32 / BF16 links and A_D^{-1}
+ * (WD_F64_COEF_F32 / WD_F64_COEF_BF16); R and Z are FP64 device block vectors
+ * and must not overlap. */
 int jacobi_precond(wd_ctx* ctx, const void* R, void* Z, int L, int j, int prec);
 
 /* Solve A X = B with preconditioned block BiCGGR (Sec. 2, algorithm box)
@@ -200,7 +209,9 @@ int bbicggr_solve(wd_ctx* ctx, const void* B, void* X, int L, double tol,
  * columns in FP64; R is ignored for mode 0.  With prec WD_F32 or WD_BF16, X
  * and R are first rounded into the library's low-precision buffers and the
  * low-precision kernel runs on them (mode 0 writes Y in FP64; mode 1 keeps
- * its low-precision output internal and leaves Y untouched). */
+ * its low-precision output internal and leaves Y untouched).  Mode 1 also
+ * takes WD_F64_COEF_F32 / WD_F64_COEF_BF16: the FP64 sweep with the links and
+ * A_D^{-1} in that format, writing Y. */
 int wd_hop_repeat(wd_ctx* ctx, const void* X, const void* R, void* Y, int L, int mode, int prec, int nrep);
 
 /* ---------------------------------------------------------------------------

@@ -33,12 +33,13 @@ WD_DIVERGED = 3
 WD_STAGNATED = 4
 
 WD_F64, WD_F32, WD_BF16 = 0, 1, 2
+WD_F64_COEF_F32, WD_F64_COEF_BF16 = 3, 4   # Jacobi only: FP64 iterates, low-precision links and A_D^-1
 WD_PRECOND_NONE, WD_PRECOND_JACOBI, WD_PRECOND_LEARNED = 0, 1, 2
 WD_LEARNED_INIT_IDENTITY, WD_LEARNED_INIT_NEUMANN = 0, 1
 WD_JACOBI_BLOCK, WD_JACOBI_POINT = 0, 1
 WD_MAX_L = 16
 
-PREC = {"f64": WD_F64, "f32": WD_F32, "bf16": WD_BF16}
+PREC = {"f64": WD_F64, "f32": WD_F32, "bf16": WD_BF16, "f64c32": WD_F64_COEF_F32, "f64cbf16": WD_F64_COEF_BF16}
 STATUS_NAME = {WD_OK: "converged", WD_NOT_CONVERGED: "not_converged", WD_BREAKDOWN: "breakdown",
                WD_DIVERGED: "diverged", WD_STAGNATED: "stagnated", WD_ENAN: "nan"}
 

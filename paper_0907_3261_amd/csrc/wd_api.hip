@@ -77,6 +77,9 @@ SmallLayout small_layout(wd_ctx* c) {
 constexpr size_t kSmallPairs = 1032 + (sizeof(Ctl) + 15) / 16 + 1;
 
 int check_prec(int prec) { return (prec == WD_F64 || prec == WD_F32 || prec == WD_BF16) ? WD_OK : WD_EINVAL; }
+// the Jacobi preconditioner also takes FP64 iterates with low-precision coefficients
+bool coef_prec(int prec) { return prec == WD_F64_COEF_F32 || prec == WD_F64_COEF_BF16; }
+Prec coef_of(int prec) { return prec == WD_F64_COEF_F32 ? Prec::F32 : Prec::BF16; }
 
 // host copy of the squared column norms of an N x L block
 int colnorms_host(wd_ctx* c, const double2* R, int L, double* out) {
@@ -299,9 +302,14 @@ int wd_apply(wd_ctx* c, const void* X, void* Y, int L, int prec) {
 
 int jacobi_precond(wd_ctx* c, const void* R, void* Z, int L, int j, int prec) {
     if (!c || !R || !Z) return WD_EINVAL;
-    if (L < 1 || L > c->max_L || j < 0 || check_prec(prec)) return WD_EINVAL;
+    if (L < 1 || L > c->max_L || j < 0 || (check_prec(prec) && !coef_prec(prec))) return WD_EINVAL;
     if (!c->have_params) return WD_ESTATE;
     if (overlap(R, Z, block_elems(c, L) * 16)) return WD_EINVAL;
+    if (coef_prec(prec)) {
+        WD_TRY_HIP(launch_jacobi_coef(c, (const double2*)R, (double2*)Z, L, j, coef_of(prec), c->stream));
+        WD_TRY_HIP(hipStreamSynchronize(c->stream));
+        return WD_OK;
+    }
     if (prec != WD_F64) {
         int r = lowp_ensure(c);
         if (r) return r;
@@ -313,10 +321,18 @@ int jacobi_precond(wd_ctx* c, const void* R, void* Z, int L, int j, int prec) {
 
 int wd_hop_repeat(wd_ctx* c, const void* X, const void* R, void* Y, int L, int mode, int prec, int nrep) {
     if (!c || !X || !Y || (mode == 1 && !R)) return WD_EINVAL;
-    if (L < 1 || L > c->max_L || check_prec(prec) || nrep < 1 || (mode != 0 && mode != 1)) return WD_EINVAL;
+    if (L < 1 || L > c->max_L || nrep < 1 || (mode != 0 && mode != 1)) return WD_EINVAL;
+    if (check_prec(prec) && !(coef_prec(prec) && mode == 1)) return WD_EINVAL;
     if (!c->have_params) return WD_ESTATE;
     const size_t bytes = block_elems(c, L) * 16;
     if (overlap(X, Y, bytes) || (mode == 1 && overlap(R, Y, bytes))) return WD_EINVAL;
+    if (coef_prec(prec)) {
+        for (int i = 0; i < nrep; ++i)
+            WD_TRY_HIP(launch_sweep_coef(c, (const double2*)X, (const double2*)R, (double2*)Y, L, coef_of(prec),
+                                         c->stream));
+        WD_TRY_HIP(hipStreamSynchronize(c->stream));
+        return WD_OK;
+    }
     if (prec != WD_F64) {
         int r = lowp_ensure(c);
         if (r) return r;
@@ -392,6 +408,7 @@ struct Solver {
     int j;
     int precond;
     Prec pin;
+    int coef = 0;  // Jacobi with FP64 iterates: 0, or the storage (Prec) of its links and A_D^{-1}
     SmallLayout sl;
     SolverBufs bufs;
     long long mvm_paper = 0, mvm_actual = 0;
@@ -411,7 +428,14 @@ struct Solver {
                                       : (double)c->g.V * (3 * (288.0 + 192.0 * L) + 2 * 96.0 * L);
             return WD_OK;
         }
-        if (precond == WD_PRECOND_JACOBI && j > 0) {
+        if (precond == WD_PRECOND_JACOBI && j > 0 && coef) {
+            WD_TRY_HIP(launch_jacobi_coef(c, in, out, L, j, (Prec)coef, c->stream));
+            mvm_actual += j - 1;
+            // FP64 vectors; links (576 B per site in FP64) and A_D^{-1} (576 B) at 1/2 or 1/4
+            const double cs = coef == (int)Prec::F32 ? 0.5 : 0.25;
+            bytes += (double)c->g.V * (bytes_first_sweep(L) - 576.0 * (1.0 - cs) +
+                                       (j - 1) * (bytes_sweep(L) - 1152.0 * (1.0 - cs)));
+        } else if (precond == WD_PRECOND_JACOBI && j > 0) {
             WD_TRY_HIP(launch_jacobi(c, in, out, L, j, pin, c->stream));
             mvm_actual += j - 1;
             const double scale = pin == Prec::F64 ? 1.0 : (pin == Prec::F32 ? 0.5 : 0.25);
@@ -453,10 +477,10 @@ int bbicggr_solve(wd_ctx* c, const void* Bv, void* Xv, int L, double tol, const 
     if (o) op = *o;
     if (op.precond != WD_PRECOND_NONE && op.precond != WD_PRECOND_JACOBI && op.precond != WD_PRECOND_LEARNED)
         return WD_EINVAL;
-    if (op.j < 0 || check_prec(op.prec_inner)) return WD_EINVAL;
+    if (op.j < 0 || (check_prec(op.prec_inner) && !coef_prec(op.prec_inner))) return WD_EINVAL;
     if (op.snap_count < 0 || (op.snap_count > 0 && (!op.x_snap || op.snap_every < 1))) return WD_EINVAL;
     if (op.precond == WD_PRECOND_LEARNED) {
-        if (op.prec_inner == WD_BF16) return WD_EINVAL;
+        if (op.prec_inner == WD_BF16 || coef_prec(op.prec_inner)) return WD_EINVAL;
         if (!c->have_theta) return WD_ESTATE;
         int r0 = learned_ensure(c);
         if (r0) return r0;
@@ -474,7 +498,7 @@ int bbicggr_solve(wd_ctx* c, const void* Bv, void* Xv, int L, double tol, const 
     if (op.snap_count > 0 && (ranges_overlap(op.x_snap, blk_bytes * op.snap_count, Bv, blk_bytes) ||
                               ranges_overlap(op.x_snap, blk_bytes * op.snap_count, Xv, blk_bytes)))
         return WD_EINVAL;
-    if (op.prec_inner != WD_F64 && op.precond == WD_PRECOND_JACOBI) {
+    if ((op.prec_inner == WD_F32 || op.prec_inner == WD_BF16) && op.precond == WD_PRECOND_JACOBI) {
         int r = lowp_ensure(c);
         if (r) return r;
     }
@@ -486,7 +510,8 @@ int bbicggr_solve(wd_ctx* c, const void* Bv, void* Xv, int L, double tol, const 
     S.nb = gram_blocks(N);
     S.j = op.j;
     S.precond = op.precond;
-    S.pin = (Prec)op.prec_inner;
+    S.coef = coef_prec(op.prec_inner) ? (int)coef_of(op.prec_inner) : 0;
+    S.pin = S.coef ? Prec::F64 : (Prec)op.prec_inner;
     S.sl = small_layout(c);
     S.bufs = SolverBufs{S.sl.C_r, S.sl.C_rn, S.sl.alpha, S.sl.gamma, S.sl.zeta, S.sl.ctl->norms,
                         &S.sl.ctl->status};
@@ -517,7 +542,7 @@ int bbicggr_solve(wd_ctx* c, const void* Bv, void* Xv, int L, double tol, const 
     bool use_x0 = op.use_x0 != 0;
     double true_rel[WD_MAX_L] = {0}, rec_rel[WD_MAX_L] = {0};
     // Krylov cycles for an inexact M (low-precision storage of the Jacobi preconditioner)
-    const bool inexact_M = op.prec_inner != WD_F64 &&
+    const bool inexact_M = (op.prec_inner == WD_F32 || op.prec_inner == WD_BF16) &&
                            (op.precond == WD_PRECOND_LEARNED || (op.precond == WD_PRECOND_JACOBI && op.j > 0));
     double cycle_tol = op.cycle_tol;
     if (cycle_tol == 0.0) cycle_tol = inexact_M ? (op.prec_inner == WD_F32 ? 1e-4 : 1e-1) : -1.0;
@@ -662,6 +687,7 @@ int bbicggr_solve(wd_ctx* c, const void* Bv, void* Xv, int L, double tol, const 
                 S.precond = fb_j > 0 ? WD_PRECOND_JACOBI : WD_PRECOND_NONE;
                 S.j = fb_j;
                 S.pin = Prec::F64;
+                S.coef = 0;
                 cycling = false;
                 fell_back = true;
                 use_x0 = false;

@@ -33,29 +33,30 @@ enum { APPLY = 0, JBLOCK = 1, JPOINT = 2 };
 // Load the 18 pairs of one chiral 6x6 Hermitian block (packed) and expand to
 // a full matrix held as 6 real diagonal entries and 15 complex upper entries.
 // C is the field base; plane k of it starts at C + k*V; boff is the site's
-// byte offset inside a plane.
-template <class S>
+// byte offset inside a plane.  S: storage of the block, R: compute type (the
+// stored values are widened on load when R is wider).
+template <class S, typename R = typename S::R>
 struct Herm6 {
-    typename S::R d[6];
-    cx<typename S::R> o[15];
+    R d[6];
+    cx<R> o[15];
     template <bool NT = false>
     __device__ __forceinline__ void load(const typename S::P* __restrict__ C, int chir, uint32_t boff, size_t V) {
 #pragma unroll
         for (int i = 0; i < 3; ++i) {
             const typename S::P* q = C + (size_t)(chir * 18 + i) * V;
             const cx<typename S::R> p = NT ? S::ldb_nt(q, boff) : S::ldb(q, boff);
-            d[2 * i] = p.re;
-            d[2 * i + 1] = p.im;
+            d[2 * i] = (R)p.re;
+            d[2 * i + 1] = (R)p.im;
         }
 #pragma unroll
         for (int p = 0; p < 15; ++p) {
             const typename S::P* q = C + (size_t)(chir * 18 + 3 + p) * V;
-            o[p] = NT ? S::ldb_nt(q, boff) : S::ldb(q, boff);
+            const cx<typename S::R> v = NT ? S::ldb_nt(q, boff) : S::ldb(q, boff);
+            o[p] = {(R)v.re, (R)v.im};
         }
     }
     // element (i, j) as a complex number
-    __device__ __forceinline__ cx<typename S::R> at(int i, int j) const {
-        using R = typename S::R;
+    __device__ __forceinline__ cx<R> at(int i, int j) const {
         if (i == j) return cx<R>{d[i], R(0)};
         if (i < j) return o[herm_index(i, j)];
         return conj(o[herm_index(j, i)]);
@@ -137,9 +138,10 @@ __device__ __forceinline__ void hop_dir(cx<R> (&acc)[12], const cx<R> (&u)[9], c
 // One hop direction for the CT columns of this thread: the link is loaded
 // once and applied to every column.  Xc is the wave-uniform base of the
 // thread's first column; link_off and nb_off are byte offsets of the link's
-// site and of the neighbour site inside one plane.
-template <class S, int MU, bool FWD, bool ADD, int CT, bool NT = false>
-__device__ __forceinline__ void hop_all(cx<typename S::R> (&acc)[CT][12], const typename S::P* __restrict__ Uk,
+// site and of the neighbour site inside one plane.  SC: storage of the links
+// (widened to the compute type of S on load).
+template <class S, int MU, bool FWD, bool ADD, int CT, bool NT = false, class SC = S>
+__device__ __forceinline__ void hop_all(cx<typename S::R> (&acc)[CT][12], const typename SC::P* __restrict__ Uk,
                                         const typename S::P* __restrict__ Xc, uint32_t link_off, uint32_t nb_off,
                                         size_t V) {
     using R = typename S::R;
@@ -148,7 +150,10 @@ __device__ __forceinline__ void hop_all(cx<typename S::R> (&acc)[CT][12], const 
     __builtin_amdgcn_sched_barrier(0);
     cx<R> u[9];
 #pragma unroll
-    for (int k = 0; k < 9; ++k) u[k] = S::ldb(Uk + (size_t)(MU * 9 + k) * V, link_off);
+    for (int k = 0; k < 9; ++k) {
+        const cx<typename SC::R> v = SC::ldb(Uk + (size_t)(MU * 9 + k) * V, link_off);
+        u[k] = {(R)v.re, (R)v.im};
+    }
 #pragma unroll
     for (int c = 0; c < CT; ++c) {
         cx<R> p[12];
@@ -164,13 +169,14 @@ __device__ __forceinline__ void store_out(typename SY::P* base, uint32_t boff, c
     SY::stb_nt(base, boff, cx<typename SY::R>{(typename SY::R)v.re, (typename SY::R)v.im});
 }
 
-// SF: storage of links, clover and the X / Rh inputs (and compute type);
-// SY: storage of the output.
+// SF: storage of the X / Rh inputs (and compute type); SY: storage of the
+// output; SC: storage of the links and clover (default SF; FP64 vectors with
+// FP32 or BF16 coefficients widen the coefficients on load).
 // NTP: bit 0 streams the clover / T^{-1} loads (read once per launch), bit 1
 // the time-direction neighbour loads (their reuse distance exceeds the L2).
-template <class SF, class SY, int CT, int MODE, int NTP = 0>
+template <class SF, class SY, int CT, int MODE, int NTP = 0, class SC = SF>
 __global__ void __launch_bounds__(256)
-    k_hop(const Geom g, const SiteMap sm, const typename SF::P* __restrict__ Uk, const typename SF::P* __restrict__ Cl,
+    k_hop(const Geom g, const SiteMap sm, const typename SC::P* __restrict__ Uk, const typename SC::P* __restrict__ Cl,
           const typename SF::P* __restrict__ X, const typename SF::P* __restrict__ Rh, typename SY::P* __restrict__ Y,
           const int col_begin, const int ntiles) {
     using R = typename SF::R;
@@ -200,14 +206,17 @@ __global__ void __launch_bounds__(256)
     const uint32_t o_ft = (uint32_t)((t == g.lt - 1) ? s - (g.lt - 1) * g.sxyz : s + g.sxyz) * PB;
     const uint32_t o_bt = (uint32_t)((t == 0) ? s + (g.lt - 1) * g.sxyz : s - g.sxyz) * PB;
     const PF* Xc = X + (size_t)c0 * cs;
+    // byte offsets of the same sites in the coefficient arrays
+    constexpr uint32_t PC = sizeof(typename SC::P);
+    const auto co = [](uint32_t o) -> uint32_t { return PC == sizeof(PF) ? o : (o / (uint32_t)sizeof(PF)) * PC; };
 
     cx<R> acc[CT][12];
     if (MODE == APPLY) {
         // acc = T X(s), one chiral block at a time
 #pragma unroll
         for (int chir = 0; chir < 2; ++chir) {
-            Herm6<SF> T;
-            T.template load<(NTP & 1) != 0>(Cl, chir, o_s, V);
+            Herm6<SC, R> T;
+            T.template load<(NTP & 1) != 0>(Cl, chir, co(o_s), V);
 #pragma unroll
             for (int c = 0; c < CT; ++c) {
                 cx<R> v[6];
@@ -233,14 +242,14 @@ __global__ void __launch_bounds__(256)
     }
 
     constexpr bool ADD = (MODE != APPLY);
-    hop_all<SF, 0, true, ADD, CT>(acc, Uk, Xc, o_s, o_fx, V);
-    hop_all<SF, 0, false, ADD, CT>(acc, Uk, Xc, o_bx, o_bx, V);
-    hop_all<SF, 1, true, ADD, CT>(acc, Uk, Xc, o_s, o_fy, V);
-    hop_all<SF, 1, false, ADD, CT>(acc, Uk, Xc, o_by, o_by, V);
-    hop_all<SF, 2, true, ADD, CT>(acc, Uk, Xc, o_s, o_fz, V);
-    hop_all<SF, 2, false, ADD, CT>(acc, Uk, Xc, o_bz, o_bz, V);
-    hop_all<SF, 3, true, ADD, CT, (NTP & 2) != 0>(acc, Uk, Xc, o_s, o_ft, V);
-    hop_all<SF, 3, false, ADD, CT, (NTP & 2) != 0>(acc, Uk, Xc, o_bt, o_bt, V);
+    hop_all<SF, 0, true, ADD, CT, false, SC>(acc, Uk, Xc, co(o_s), o_fx, V);
+    hop_all<SF, 0, false, ADD, CT, false, SC>(acc, Uk, Xc, co(o_bx), o_bx, V);
+    hop_all<SF, 1, true, ADD, CT, false, SC>(acc, Uk, Xc, co(o_s), o_fy, V);
+    hop_all<SF, 1, false, ADD, CT, false, SC>(acc, Uk, Xc, co(o_by), o_by, V);
+    hop_all<SF, 2, true, ADD, CT, false, SC>(acc, Uk, Xc, co(o_s), o_fz, V);
+    hop_all<SF, 2, false, ADD, CT, false, SC>(acc, Uk, Xc, co(o_bz), o_bz, V);
+    hop_all<SF, 3, true, ADD, CT, (NTP & 2) != 0, SC>(acc, Uk, Xc, co(o_s), o_ft, V);
+    hop_all<SF, 3, false, ADD, CT, (NTP & 2) != 0, SC>(acc, Uk, Xc, co(o_bt), o_bt, V);
     __builtin_amdgcn_sched_barrier(0);
 
     PY* Yc = Y + (size_t)c0 * cs;
@@ -252,8 +261,8 @@ __global__ void __launch_bounds__(256)
     } else {
 #pragma unroll
         for (int chir = 0; chir < 2; ++chir) {
-            Herm6<SF> T;
-            T.template load<(NTP & 1) != 0>(Cl, chir, o_s, V);
+            Herm6<SC, R> T;
+            T.template load<(NTP & 1) != 0>(Cl, chir, co(o_s), V);
 #pragma unroll
             for (int c = 0; c < CT; ++c) {
                 {
@@ -287,12 +296,13 @@ __global__ void __launch_bounds__(256)
 }
 
 // First Jacobi sweep from G_0 = 0: Y = A_D^{-1} R (site-local, no hop).
-// SI: input storage, SF: clover storage and compute, SY: output storage;
-// with RL != nullptr the input is also written out in format SF (the
+// SI: input storage, SF: compute (and clover) storage, SY: output storage,
+// SC: clover storage when it differs from SF (widened on load); with
+// RL != nullptr the input is also written out in format SF (the
 // low-precision copy of the right-hand side used by later sweeps).
-template <class SI, class SF, class SY, int MODE>
+template <class SI, class SF, class SY, int MODE, class SC = SF>
 __global__ void __launch_bounds__(256)
-    k_first_sweep(const Geom g, const typename SF::P* __restrict__ Cl, const typename SI::P* __restrict__ Rin,
+    k_first_sweep(const Geom g, const typename SC::P* __restrict__ Cl, const typename SI::P* __restrict__ Rin,
                   typename SF::P* __restrict__ RL, typename SY::P* __restrict__ Y, const int L) {
     // one thread per site; the site's A_D^{-1} block stays in registers for all L columns
     using R = typename SF::R;
@@ -303,10 +313,11 @@ __global__ void __launch_bounds__(256)
     const uint32_t oF = (uint32_t)s * sizeof(typename SF::P);
     const uint32_t oI = (uint32_t)s * sizeof(typename SI::P);
     const uint32_t oY = (uint32_t)s * sizeof(typename SY::P);
+    const uint32_t oC = (uint32_t)s * sizeof(typename SC::P);
 #pragma unroll
     for (int chir = 0; chir < 2; ++chir) {
-        Herm6<SF> T;
-        T.load(Cl, chir, oF, V);
+        Herm6<SC, R> T;
+        T.load(Cl, chir, oC, V);
         for (int col = 0; col < L; ++col) {
             const typename SI::P* Rc = Rin + (size_t)col * cs;
             cx<R> v[6];
@@ -370,52 +381,53 @@ int tile_cols(int L, bool lowp) {
     return 4;
 }
 
-template <class SF, class SY, int MODE, int CT>
+template <class SF, class SY, int MODE, int CT, class SC = SF>
 hipError_t launch_hop_ct(const Geom& g, const void* Uk, const void* Cl, const void* X, const void* Rh, void* Y,
                          int col_begin, int ntiles, hipStream_t s) {
     if (ntiles > 4) return hipErrorInvalidValue;  // at most 4 wavefronts (256 threads) per site tile
-    const double bytes_site = 12.0 * CT * ntiles * sizeof(typename SF::P) + 72.0 * sizeof(typename SF::P);
+    const double bytes_site = 12.0 * CT * ntiles * sizeof(typename SF::P) + 72.0 * sizeof(typename SC::P);
     const SiteMap sm = make_site_map(g, bytes_site);
     dim3 block(64, ntiles), grid(sm.nblk);
     using PF = typename SF::P;
     using PY = typename SY::P;
+    using PC = typename SC::P;
     const int ntp = hop_ntp();
     if constexpr (CT == 3) {
         if (ntp == 0)
-            k_hop<SF, SY, CT, MODE, 0><<<grid, block, 0, s>>>(g, sm, (const PF*)Uk, (const PF*)Cl, (const PF*)X,
+            k_hop<SF, SY, CT, MODE, 0, SC><<<grid, block, 0, s>>>(g, sm, (const PC*)Uk, (const PC*)Cl, (const PF*)X,
                                                               (const PF*)Rh, (PY*)Y, col_begin, ntiles);
         else if (ntp == 1)
-            k_hop<SF, SY, CT, MODE, 1><<<grid, block, 0, s>>>(g, sm, (const PF*)Uk, (const PF*)Cl, (const PF*)X,
+            k_hop<SF, SY, CT, MODE, 1, SC><<<grid, block, 0, s>>>(g, sm, (const PC*)Uk, (const PC*)Cl, (const PF*)X,
                                                               (const PF*)Rh, (PY*)Y, col_begin, ntiles);
         else if (ntp == 3)
-            k_hop<SF, SY, CT, MODE, 3><<<grid, block, 0, s>>>(g, sm, (const PF*)Uk, (const PF*)Cl, (const PF*)X,
+            k_hop<SF, SY, CT, MODE, 3, SC><<<grid, block, 0, s>>>(g, sm, (const PC*)Uk, (const PC*)Cl, (const PF*)X,
                                                               (const PF*)Rh, (PY*)Y, col_begin, ntiles);
         else
-            k_hop<SF, SY, CT, MODE, 2><<<grid, block, 0, s>>>(g, sm, (const PF*)Uk, (const PF*)Cl, (const PF*)X,
+            k_hop<SF, SY, CT, MODE, 2, SC><<<grid, block, 0, s>>>(g, sm, (const PC*)Uk, (const PC*)Cl, (const PF*)X,
                                                               (const PF*)Rh, (PY*)Y, col_begin, ntiles);
     } else {
         (void)ntp;
-        k_hop<SF, SY, CT, MODE, 2><<<grid, block, 0, s>>>(g, sm, (const PF*)Uk, (const PF*)Cl, (const PF*)X,
+        k_hop<SF, SY, CT, MODE, 2, SC><<<grid, block, 0, s>>>(g, sm, (const PC*)Uk, (const PC*)Cl, (const PF*)X,
                                                           (const PF*)Rh, (PY*)Y, col_begin, ntiles);
     }
     return hipGetLastError();
 }
 
-template <class SF, class SY, int MODE>
+template <class SF, class SY, int MODE, class SC = SF>
 hipError_t launch_hop_cols(const Geom& g, const void* Uk, const void* Cl, const void* X, const void* Rh, void* Y,
                            int CT, int col_begin, int ntiles, hipStream_t s) {
     switch (CT) {
-        case 1: return launch_hop_ct<SF, SY, MODE, 1>(g, Uk, Cl, X, Rh, Y, col_begin, ntiles, s);
-        case 2: return launch_hop_ct<SF, SY, MODE, 2>(g, Uk, Cl, X, Rh, Y, col_begin, ntiles, s);
-        case 3: return launch_hop_ct<SF, SY, MODE, 3>(g, Uk, Cl, X, Rh, Y, col_begin, ntiles, s);
-        case 4: return launch_hop_ct<SF, SY, MODE, 4>(g, Uk, Cl, X, Rh, Y, col_begin, ntiles, s);
+        case 1: return launch_hop_ct<SF, SY, MODE, 1, SC>(g, Uk, Cl, X, Rh, Y, col_begin, ntiles, s);
+        case 2: return launch_hop_ct<SF, SY, MODE, 2, SC>(g, Uk, Cl, X, Rh, Y, col_begin, ntiles, s);
+        case 3: return launch_hop_ct<SF, SY, MODE, 3, SC>(g, Uk, Cl, X, Rh, Y, col_begin, ntiles, s);
+        case 4: return launch_hop_ct<SF, SY, MODE, 4, SC>(g, Uk, Cl, X, Rh, Y, col_begin, ntiles, s);
         default: return hipErrorInvalidValue;
     }
 }
 
 // L columns: launches of up to four tiles of CT columns, then one launch for
 // the remainder (fewer than CT columns).
-template <class SF, class SY, int MODE>
+template <class SF, class SY, int MODE, class SC = SF>
 hipError_t launch_hop_t(const Geom& g, const void* Uk, const void* Cl, const void* X, const void* Rh, void* Y, int L,
                         hipStream_t s) {
     const int CT = tile_cols(L, sizeof(typename SF::P) < 16);
@@ -423,31 +435,48 @@ hipError_t launch_hop_t(const Geom& g, const void* Uk, const void* Cl, const voi
     hipError_t e = hipSuccess;
     for (int t0 = 0; t0 < full && e == hipSuccess; t0 += 4) {
         const int nt = full - t0 < 4 ? full - t0 : 4;
-        e = launch_hop_cols<SF, SY, MODE>(g, Uk, Cl, X, Rh, Y, CT, t0 * CT, nt, s);
+        e = launch_hop_cols<SF, SY, MODE, SC>(g, Uk, Cl, X, Rh, Y, CT, t0 * CT, nt, s);
     }
     if (e != hipSuccess || rem == 0) return e;
-    return launch_hop_cols<SF, SY, MODE>(g, Uk, Cl, X, Rh, Y, rem, full * CT, 1, s);
+    return launch_hop_cols<SF, SY, MODE, SC>(g, Uk, Cl, X, Rh, Y, rem, full * CT, 1, s);
 }
 
-template <class SI, class SF, class SY>
+template <class SI, class SF, class SY, class SC = SF>
 hipError_t launch_first(const wd_ctx* c, const void* Cl, const void* Rin, void* RL, void* Y, int L, hipStream_t s) {
     const unsigned nb = (unsigned)((c->g.V + 255) / 256);
     if (c->jacobi_kind == WD_JACOBI_POINT)
-        k_first_sweep<SI, SF, SY, JPOINT><<<nb, 256, 0, s>>>(c->g, (const typename SF::P*)Cl,
-                                                              (const typename SI::P*)Rin, (typename SF::P*)RL,
-                                                              (typename SY::P*)Y, L);
+        k_first_sweep<SI, SF, SY, JPOINT, SC><<<nb, 256, 0, s>>>(c->g, (const typename SC::P*)Cl,
+                                                                  (const typename SI::P*)Rin, (typename SF::P*)RL,
+                                                                  (typename SY::P*)Y, L);
     else
-        k_first_sweep<SI, SF, SY, JBLOCK><<<nb, 256, 0, s>>>(c->g, (const typename SF::P*)Cl,
-                                                              (const typename SI::P*)Rin, (typename SF::P*)RL,
-                                                              (typename SY::P*)Y, L);
+        k_first_sweep<SI, SF, SY, JBLOCK, SC><<<nb, 256, 0, s>>>(c->g, (const typename SC::P*)Cl,
+                                                                  (const typename SI::P*)Rin, (typename SF::P*)RL,
+                                                                  (typename SY::P*)Y, L);
     return hipGetLastError();
 }
 
-template <class SF, class SY>
+template <class SF, class SY, class SC = SF>
 hipError_t launch_sweep(const wd_ctx* c, int pi, const void* X, const void* Rh, void* Y, int L, hipStream_t s) {
     if (c->jacobi_kind == WD_JACOBI_POINT)
-        return launch_hop_t<SF, SY, JPOINT>(c->g, c->f.Uk[pi], c->f.Tp[pi], X, Rh, Y, L, s);
-    return launch_hop_t<SF, SY, JBLOCK>(c->g, c->f.Uk[pi], c->f.Ti[pi], X, Rh, Y, L, s);
+        return launch_hop_t<SF, SY, JPOINT, SC>(c->g, c->f.Uk[pi], c->f.Tp[pi], X, Rh, Y, L, s);
+    return launch_hop_t<SF, SY, JBLOCK, SC>(c->g, c->f.Uk[pi], c->f.Ti[pi], X, Rh, Y, L, s);
+}
+
+// j sweeps with FP64 vectors and arithmetic and the links and A_D^{-1} of
+// storage format SC (FP32 or BF16): a fixed linear operator, unlike the
+// low-precision form, whose rounding of the vectors makes it nonlinear.
+template <class SC>
+hipError_t jacobi_coef(wd_ctx* c, int pi, const double2* R, double2* Z, int L, int j, hipStream_t s) {
+    const void* clf = (c->jacobi_kind == WD_JACOBI_POINT) ? c->f.Tp[pi] : c->f.Ti[pi];
+    double2* tmp = c->ws[10];
+    double2* out = ((j - 1) % 2 == 0) ? Z : tmp;
+    hipError_t e = launch_first<StF64, StF64, StF64, SC>(c, clf, R, nullptr, out, L, s);
+    for (int i = 2; i <= j && e == hipSuccess; ++i) {
+        double2* in = out;
+        out = ((j - i) % 2 == 0) ? Z : tmp;
+        e = launch_sweep<StF64, StF64, SC>(c, pi, in, R, out, L, s);
+    }
+    return e;
 }
 
 // j sweeps in storage format S (FP32 or BF16), FP64 in and out.
@@ -477,6 +506,13 @@ hipError_t launch_sweep_f64(const wd_ctx* c, const double2* X, const double2* R,
     return launch_sweep<StF64, StF64>(c, 0, X, R, Y, L, s);
 }
 
+hipError_t launch_sweep_coef(const wd_ctx* c, const double2* X, const double2* R, double2* Y, int L, Prec coef,
+                             hipStream_t s) {
+    if (coef == Prec::F32) return launch_sweep<StF64, StF64, StF32>(c, 1, X, R, Y, L, s);
+    if (coef == Prec::BF16) return launch_sweep<StF64, StF64, StBF16>(c, 2, X, R, Y, L, s);
+    return hipErrorInvalidValue;
+}
+
 hipError_t launch_apply_A_lowp(wd_ctx* c, const double2* X, double2* Y, int L, Prec p, hipStream_t s) {
     const size_t n = (size_t)12 * c->g.V * L;
     hipError_t e = launch_to_lowp(X, c->lp[0], p, n, s);
@@ -484,6 +520,13 @@ hipError_t launch_apply_A_lowp(wd_ctx* c, const double2* X, double2* Y, int L, P
     if (p == Prec::F32)
         return launch_hop_t<StF32, StF64, APPLY>(c->g, c->f.Uk[1], c->f.Tc[1], c->lp[0], nullptr, Y, L, s);
     return launch_hop_t<StBF16, StF64, APPLY>(c->g, c->f.Uk[2], c->f.Tc[2], c->lp[0], nullptr, Y, L, s);
+}
+
+hipError_t launch_jacobi_coef(wd_ctx* c, const double2* R, double2* Z, int L, int j, Prec coef, hipStream_t s) {
+    if (j == 0) return launch_copy(Z, R, (size_t)12 * c->g.V * L, s);
+    if (coef == Prec::F32) return jacobi_coef<StF32>(c, 1, R, Z, L, j, s);
+    if (coef == Prec::BF16) return jacobi_coef<StBF16>(c, 2, R, Z, L, j, s);
+    return hipErrorInvalidValue;
 }
 
 hipError_t launch_jacobi(wd_ctx* c, const double2* R, double2* Z, int L, int j, Prec p, hipStream_t s) {

@@ -315,6 +315,11 @@ hipError_t launch_to_lowp(const double2* src, void* dst, Prec p, size_t n, hipSt
 hipError_t launch_apply_A(const wd_ctx* c, const double2* X, double2* Y, int L, hipStream_t s);
 // Z = M R with j sweeps in precision p; tmp is a scratch block of L columns
 hipError_t launch_jacobi(wd_ctx* c, const double2* R, double2* Z, int L, int j, Prec p, hipStream_t s);
+// Z = M R with j sweeps of FP64 vectors and arithmetic, links and A_D^{-1} stored in precision coef
+hipError_t launch_jacobi_coef(wd_ctx* c, const double2* R, double2* Z, int L, int j, Prec coef, hipStream_t s);
+// one such sweep (FP64 vectors, coefficients in precision coef)
+hipError_t launch_sweep_coef(const wd_ctx* c, const double2* X, const double2* R, double2* Y, int L, Prec coef,
+                             hipStream_t s);
 // one Jacobi sweep Y = A_D^{-1}(R + kappa H X) in FP64
 hipError_t launch_sweep_f64(const wd_ctx* c, const double2* X, const double2* R, double2* Y, int L, hipStream_t s);
 // algorithmic HBM bytes per site of the kernels (FP64 storage, L columns)
