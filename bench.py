@@ -86,10 +86,11 @@ def traffic_from_profiles(mode: int):
         if d.get("src_hash") != src_hash():
             return None
         for k, v in d.get("bytes_per_launch", {}).items():
-            # template arguments of the hop kernel: storage in, storage out, columns, mode, stream policy
+            # template arguments of the hop kernel: storage in, storage out, columns, mode, stream
+            # policy, coefficient storage
             if k.startswith("void k_hop<StF64, StF64,"):
                 args = [a.strip() for a in k[k.index("<") + 1:k.rindex(">")].split(",")]
-                if len(args) >= 4 and args[3] == str(mode):
+                if len(args) >= 4 and args[3] == str(mode) and (len(args) < 6 or args[5] == "StF64"):
                     return v
     except Exception:
         return None
