@@ -138,8 +138,8 @@ def compare_leg(ctx, torch, np, B, L, w, a):
     for prec in ("f64", "f32", "bf16", "f64c32", "f64cbf16"):
         torch.cuda.synchronize()
         # rounded coefficients give a fixed M but can stagnate near the critical kappa: one run,
-        # capped at three times the FP64 iterations
-        cap = dict(max_iter=3 * k64 + 10, max_restarts=0) if prec.startswith("f64c") else {}
+        # capped at one and a half times the FP64 iterations
+        cap = dict(max_iter=3 * k64 // 2 + 10, max_restarts=0) if prec.startswith("f64c") else {}
         X, info = ctx.solve(B, tol=w["tol"], j=a.j, prec_inner=prec, **cap)
         if prec == "f64":
             k64 = info["iterations"]
