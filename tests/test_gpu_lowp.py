@@ -210,3 +210,27 @@ def test_low_precision_coefficients_solve(pkg, prec):
     assert np.max(tr) <= 1e-12
     assert info["iterations"] <= i64["iterations"] + 3
     c.close()
+
+
+@pytest.mark.parametrize("prec", ["f64c32", "f64cbf16"])
+def test_jacobi_low_precision_coefficients_point_diagonal(pkg, prec):
+    """The point-diagonal reading of A_D with rounded coefficients, against the oracle's
+    point-diagonal Jacobi, and linear."""
+    dims = (4, 6, 4, 8)
+    U = wi.random_links(dims, 0.3, 306)
+    c = pkg.Context(dims, bc_t=1, max_L=12)
+    c.set_links(U)
+    c.set_params(0.12, 1.6, 1)
+    op = WilsonClover(dims, U, 0.12, 1.6, bc_t=1, jacobi_kind="point")
+    j = 3
+    R1 = torch.from_numpy(wi.gaussian_block(op.V, 2, 307)).cuda()
+    R2 = torch.from_numpy(wi.gaussian_block(op.V, 2, 308)).cuda()
+    Z1 = c.jacobi(R1, j, prec=prec)
+    Z12 = c.jacobi(R1 - 3 * R2, j, prec=prec)
+    Z2 = c.jacobi(R2, j, prec=prec)
+    lin = float(torch.max(torch.abs(Z12 - Z1 + 3 * Z2)) / torch.max(torch.abs(Z12)))
+    assert lin < 1e-13
+    err = _maxrel(Z1.cpu().numpy(), op.to_block(jacobi_apply(op, op.from_block(R1.cpu().numpy()), j)))
+    _record(f"jacobi_point_{prec}_j{j}", err)
+    assert (1e-11 if prec == "f64c32" else 1e-6) < err < j * COEF_TOL[prec]
+    c.close()
