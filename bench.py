@@ -60,6 +60,9 @@ def parse():
     p.add_argument("--kappa-heavy", type=float, default=0.12,
                    help="second kappa (heavier quark) for the time-to-solution comparison; 0 skips it")
     p.add_argument("--no-cpu-baseline", action="store_true")
+    p.add_argument("--ensembles", type=int, default=0,
+                   help="compare the preconditioner precisions over this many link ensembles (link seeds) "
+                        "at --kappa and --kappa-heavy: converged counts and mean s/RHS")
     p.add_argument("--kernels-only", action="store_true",
                    help="only the hopping-kernel launches and a plain copy (for rocprofv3 counter runs)")
     return p.parse_args()
@@ -244,6 +247,57 @@ def learned_solves(ctx, torch, np, B, L, w, a, thetas, Xref):
     return out
 
 
+def ensemble_sweep(pkg, wi, torch, np, w, a, kappa, L, V, B):
+    """Every preconditioner precision on a.ensembles link ensembles (seeds link_seed + e) with
+    the workload's sources, at kappa and a.kappa_heavy, as the paper averages over gauge
+    configurations (Tables 1 and 2): per precision the number of runs that reach the FP64 1e-12
+    true residual and the mean iterations and seconds per RHS over those."""
+    from paper_0907_3261_amd import WD_PRECOND_LEARNED
+    modes = [("jacobi_f64", "f64", None), ("jacobi_f32", "f32", None), ("jacobi_bf16", "bf16", None),
+             ("jacobi_f64c32", "f64c32", None), ("jacobi_f64cbf16", "f64cbf16", None),
+             ("learned_neumann_f64", "f64", WD_PRECOND_LEARNED), ("learned_neumann_f32", "f32", WD_PRECOND_LEARNED)]
+    runs = {}
+    for e in range(a.ensembles):
+        U = wi.random_links(w["dims"], w["eps"], w["link_seed"] + e)
+        ctx = pkg.Context(w["dims"], bc_t=w["bc_t"], max_L=L)
+        ctx.set_links(U)
+        del U
+        for kp in [kappa] + ([a.kappa_heavy] if a.kappa_heavy > 0 else []):
+            ctx.set_params(kp, w["csw"])
+            ctx.learned_init("neumann")
+            k64 = 0
+            for name, prec, pc in modes:
+                kw = dict(precond=pc) if pc is not None else {}
+                if prec.startswith("f64c"):
+                    kw.update(max_iter=3 * k64 // 2 + 10, max_restarts=0)
+                X, info = ctx.solve(B, tol=w["tol"], j=a.j, prec_inner=prec, **kw)
+                ok = info["status"] == "converged" and float(np.max(info["true_residual"])) <= w["tol"]
+                if name == "jacobi_f64":
+                    k64 = info["iterations"]
+                runs.setdefault(f"kappa{kp}", {}).setdefault(name, []).append(
+                    {"ensemble": e, "ok": bool(ok), "iterations": int(info["total_iterations"]),
+                     "fallback": bool(info["fallback"]), "s_per_rhs": info["seconds"] / L})
+                print(f"[bench] ensemble {e} kappa {kp} {name}: {info['status']} k={info['total_iterations']} "
+                      f"{info['seconds'] / L:.4f} s/RHS", file=sys.stderr, flush=True)
+                del X
+        ctx.close()
+        torch.cuda.empty_cache()
+    summary = {}
+    for kk, per in runs.items():
+        summary[kk] = {}
+        base = [r["s_per_rhs"] for r in per["jacobi_f64"] if r["ok"]]
+        for name, rs in per.items():
+            good = [r for r in rs if r["ok"]]
+            rec = {"converged": f"{len(good)}/{len(rs)}", "fallbacks": sum(r["fallback"] for r in rs)}
+            if good:
+                rec["mean_iterations"] = round(float(np.mean([r["iterations"] for r in good])), 1)
+                rec["mean_s_per_rhs"] = round(float(np.mean([r["s_per_rhs"] for r in good])), 5)
+                if base:
+                    rec["speedup_vs_f64_jacobi_mean"] = round(float(np.mean(base)) / rec["mean_s_per_rhs"], 3)
+            summary[kk][name] = rec
+    return {"ensembles": summary, "workload": a.workload, "L": L, "j": a.j, "runs": runs}
+
+
 def cpu_baseline(w, kappa):
     """Oracle A X on a 32 x 32 x 32 x 2 slab of the workload's ensemble, twelve columns."""
     import numpy as np
@@ -313,6 +367,10 @@ def main():
                 print(f"[bench] j-sweep kappa={kp} j={j}: {out[f'kappa{kp}_j{j}']}", file=sys.stderr, flush=True)
         print(json.dumps({"j_sweep": out, "workload": a.workload, "L": L}), flush=True)
         ctx.close()
+        return
+    if a.ensembles > 0:
+        ctx.close()
+        print(json.dumps(ensemble_sweep(pkg, wi, torch, np, w, a, kappa, L, V, B)), flush=True)
         return
     if a.kernels_only:
         ms_sweep = time_hop(ctx, torch, V, L, 1, a.hop_reps)
