@@ -107,13 +107,14 @@ def test_hop_repeat_lowp_runs_the_apply_kernel(pkg, prec):
 
 
 @pytest.mark.parametrize("prec", ["f32", "bf16"])
-@pytest.mark.parametrize("j", [1, 2, 4, 12])
-def test_jacobi_lowp(pkg, prec, j):
+@pytest.mark.parametrize("j,L", [(1, 4), (2, 4), (4, 4), (12, 4), (3, 12)])
+def test_jacobi_lowp(pkg, prec, j, L):
+    """L = 4 runs two-column tiles, L = 12 the four-column tiles of the benchmark workload."""
     c, op = _setup(pkg)
-    R = wi.gaussian_block(op.V, 4, 303)
+    R = wi.gaussian_block(op.V, L, 303)
     Z = c.jacobi(torch.from_numpy(R).cuda(), j, prec=prec).cpu().numpy()
     err = _maxrel(Z, op.to_block(jacobi_apply(op, op.from_block(R), j)))
-    _record(f"jacobi_{prec}_j{j}", err)
+    _record(f"jacobi_{prec}_j{j}_L{L}", err)
     assert err < j * SWEEP_TOL[prec]
     c.close()
 
@@ -169,22 +170,23 @@ def test_stalled_cycles_keep_best_iterate(pkg):
 
 
 @pytest.mark.parametrize("prec", ["f64c32", "f64cbf16"])
-@pytest.mark.parametrize("j", [1, 2, 5, 12])
-def test_jacobi_low_precision_coefficients(pkg, prec, j):
+@pytest.mark.parametrize("j,L", [(1, 3), (2, 3), (5, 3), (12, 3), (3, 12)])
+def test_jacobi_low_precision_coefficients(pkg, prec, j, L):
     """FP64 iterates with rounded links and A_D^{-1}: within the derived bound of the FP64
-    oracle, visibly not FP64, and linear to FP64 rounding."""
+    oracle, visibly not FP64, and linear to FP64 rounding.  L = 12 runs the three-column tiles
+    of the benchmark workload."""
     c, op = _setup(pkg)
-    R1 = wi.gaussian_block(op.V, 3, 304)
-    R2 = wi.gaussian_block(op.V, 3, 305)
+    R1 = wi.gaussian_block(op.V, L, 304)
+    R2 = wi.gaussian_block(op.V, L, 305)
     d1, d2 = torch.from_numpy(R1).cuda(), torch.from_numpy(R2).cuda()
     Z1 = c.jacobi(d1, j, prec=prec)
     Z2 = c.jacobi(d2, j, prec=prec)
     Z12 = c.jacobi(d1 + 2 * d2, j, prec=prec)
     lin = float(torch.max(torch.abs(Z12 - Z1 - 2 * Z2)) / torch.max(torch.abs(Z12)))
-    _record(f"jacobi_{prec}_j{j}_linearity", lin)
+    _record(f"jacobi_{prec}_j{j}_L{L}_linearity", lin)
     assert lin < 1e-13
     err = _maxrel(Z1.cpu().numpy(), op.to_block(jacobi_apply(op, op.from_block(R1), j)))
-    _record(f"jacobi_{prec}_j{j}", err)
+    _record(f"jacobi_{prec}_j{j}_L{L}", err)
     assert err < j * COEF_TOL[prec]
     assert err > (1e-11 if prec == "f64c32" else 1e-6)      # the coefficients really are rounded
     c.close()

@@ -393,3 +393,34 @@ def test_full_size_jacobi_two_sweeps_sampled(pkg, big):
         g1 = lambda t: Tinv[t] @ Rs[:, :, pos[t]].T             # noqa: E731
         ref = Tinv[s] @ (Rs[:, :, pos[s]].T + w["kappa"] * so.hop_at(s, g1))
         assert _maxrel(Zs[:, :, k].T, ref) < 1e-13
+
+
+@pytest.mark.parametrize("prec,tol", [("f32", 2e3 * 2.0 ** -24), ("bf16", 18 * 2.0 ** -8),
+                                      ("f64c32", 9 * 2.0 ** -24), ("f64cbf16", 9 * 2.0 ** -8)])
+def test_full_size_jacobi_two_sweeps_sampled_low_precision(pkg, big, prec, tol):
+    """The low-precision Jacobi kernels in the benchmark's launch configuration (32^3 x 64,
+    twelve columns), at sampled sites against the FP64 site operator, within twice the
+    per-sweep bound derived for each storage format (rounded iterates: 1e3 u32 and 9 u_bf16
+    per sweep; rounded coefficients only: 4.5 u)."""
+    w, c, U = big
+    V = wi.volume(w["dims"])
+    g = torch.Generator(device="cuda").manual_seed(7)
+    R = torch.complex(torch.randn((12, 12, V), generator=g, device="cuda", dtype=torch.float64),
+                      torch.randn((12, 12, V), generator=g, device="cuda", dtype=torch.float64))
+    Z = c.jacobi(R, 2, prec=prec)
+    so = SiteOperator(w["dims"], U, w["kappa"], w["csw"], w["bc_t"])
+    sites = _sample_sites(V, 8, 10)
+    need = sorted(set(sites) | {n for s in sites for (_, _, n, _) in so.neighbours(s)})
+    Rs = R[:, :, torch.tensor(need, device="cuda")].cpu().numpy()
+    pos = {s: i for i, s in enumerate(need)}
+    Zs = Z[:, :, torch.tensor(sites, device="cuda")].cpu().numpy()
+    del R, Z
+    Tinv = {s: np.linalg.inv(so.T(s)) for s in need}
+    ref, got = [], []
+    for k, s in enumerate(sites):
+        g1 = lambda t: Tinv[t] @ Rs[:, :, pos[t]].T             # noqa: E731
+        ref.append(Tinv[s] @ (Rs[:, :, pos[s]].T + w["kappa"] * so.hop_at(s, g1)))
+        got.append(Zs[:, :, k].T)
+    err = _maxrel(np.stack(got), np.stack(ref))
+    _say(f"full-size Jacobi j=2 {prec}: {err:.2e}")
+    assert err < tol
