@@ -32,8 +32,8 @@ def _say(msg):
 
 def _record(key, val):
     _REC[key] = val
-    out = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), "gpurun_out")
-    if os.path.isdir(out):
+    out = os.environ.get("WDSOLVE_RESULTS_DIR")      # optional: keep the measured values as JSON
+    if out and os.path.isdir(out):
         with open(os.path.join(out, "lsweep.json"), "w") as f:
             json.dump(_REC, f, indent=1)
 

@@ -52,8 +52,8 @@ RESULTS = {}
 def _record(key, val):
     RESULTS[key] = float(val)
     sys.__stderr__.write(f"[lowp] {key} = {val:.3e}\n")
-    out = os.path.join(os.environ.get("GRAFT_REPO_ROOT", "."), "gpurun_out")
-    if os.path.isdir(out):
+    out = os.environ.get("WDSOLVE_RESULTS_DIR")      # optional: keep the measured errors as JSON
+    if out and os.path.isdir(out):
         with open(os.path.join(out, "lowp_errors.json"), "w") as f:
             json.dump(RESULTS, f, indent=1)
 
