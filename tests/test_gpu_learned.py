@@ -183,6 +183,8 @@ def test_training_lowers_loss_and_solves(pkg, prec):
     Ep = torch.from_numpy(wi.gaussian_block(op.V, 24, 407)).cuda()
     Rp = torch.cat([c.apply(Ep[i:i + L]) for i in range(0, 24, L)]).contiguous()
     c.learned_init("neumann")
+    Xn, i_neu = c.solve(B, tol=1e-12, precond=pkg.WD_PRECOND_LEARNED, prec_inner=prec)
+    assert i_neu["status"] == "converged", i_neu
     hist = c.learned_train(Rp, Ep, L, steps=40, lr=1e-3)
     _say(f"train loss {hist[:4]} -> {hist[-4:]}")
     assert np.all(np.isfinite(hist))
@@ -193,10 +195,14 @@ def test_training_lowers_loss_and_solves(pkg, prec):
     assert np.max(tr) <= 1e-12
     X0, i0 = c.solve(B, tol=1e-12, j=0)
     assert i0["status"] == "converged"
-    _say(f"iterations: learned M {info['total_iterations']} (cycles {info['cycles']}), M = 1 {i0['iterations']}")
+    _say(f"iterations: trained M {info['total_iterations']} (cycles {info['cycles']}), Neumann start "
+         f"{i_neu['total_iterations']}, M = 1 {i0['iterations']}")
     assert info["total_iterations"] < i0["iterations"]
     if prec == "f64":
         assert info["cycles"] == 1 and not info["fallback"]
+        # against the untrained (Neumann) start of the same network: here the lower loss does not
+        # buy iterations (measured 26 against 25), so only a clear loss of quality would fail
+        assert info["iterations"] <= 1.2 * i_neu["iterations"] + 1
     c.close()
 
 
