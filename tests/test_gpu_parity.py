@@ -424,3 +424,48 @@ def test_full_size_jacobi_two_sweeps_sampled_low_precision(pkg, big, prec, tol):
     err = _maxrel(np.stack(got), np.stack(ref))
     _say(f"full-size Jacobi j=2 {prec}: {err:.2e}")
     assert err < tol
+
+
+def test_kappa_zero_is_identity(pkg):
+    """kappa = 0: A = 1, A_D = 1 and the operator and every Jacobi application return their
+    input bit for bit; the solver then converges in one iteration with X = B to rounding."""
+    dims = (4, 4, 2, 6)
+    U = wi.random_links(dims, 0.5, 150)
+    c = _ctx(pkg, dims, U, 0.0, 1.7, 1)
+    V = wi.volume(dims)
+    Xd = _dev(wi.gaussian_block(V, 5, 151))
+    assert torch.equal(c.apply(Xd), Xd)
+    # j sweeps of G <- R + 0 * H G from G_0 = 0 with A_D = 1 give R exactly
+    for j in (1, 2, 7):
+        assert torch.equal(c.jacobi(Xd, j), Xd)
+    X, info = c.solve(Xd, tol=1e-12, j=3)
+    assert info["status"] == "converged" and info["iterations"] <= 1
+    assert _maxrel(_host(X), _host(Xd)) < 1e-14          # the L x L coefficients are 1 up to rounding
+    c.close()
+
+
+@pytest.mark.parametrize("n", [(0, 0, 0, 0), (1, 0, 2, 1), (3, 1, 1, 5)])
+def test_free_field_plane_wave(pkg, n):
+    """Unit links: A e^{ipx} u = [1 - 2 kappa sum cos p_mu + 2 i kappa sum gamma_mu sin p_mu] e^{ipx} u
+    with p_mu = 2 pi n_mu / L_mu (periodic), checked on the GPU against the closed form."""
+    from oracle import gammas
+    dims = (4, 3, 4, 6)
+    V = wi.volume(dims)
+    kappa = 0.11
+    U = np.zeros((4, V, 3, 3), dtype=np.complex128)
+    U[:, :] = np.eye(3)
+    c = _ctx(pkg, dims, U, kappa, 1.3, 0)
+    p = [2 * np.pi * n[m] / dims[m] for m in range(4)]
+    s = np.arange(V)
+    x = [s % dims[0], (s // dims[0]) % dims[1], (s // (dims[0] * dims[1])) % dims[2], s // (dims[0] * dims[1] * dims[2])]
+    phase = np.exp(1j * sum(p[m] * x[m] for m in range(4)))            # (V,)
+    rng = np.random.default_rng(152)
+    u = rng.standard_normal((2, 12)) + 1j * rng.standard_normal((2, 12))  # two columns, row 3*spin + colour
+    B = u[:, :, None] * phase[None, None, :]
+    g = gammas()
+    M4 = (1 - 2 * kappa * sum(np.cos(pm) for pm in p)) * np.eye(4) + 2j * kappa * sum(g[m] * np.sin(p[m]) for m in range(4))
+    M12 = np.kron(M4, np.eye(3))
+    expect = (u @ M12.T)[:, :, None] * phase[None, None, :]
+    Y = _host(c.apply(_dev(B)))
+    assert _maxrel(Y, expect) < 1e-13
+    c.close()
