@@ -444,18 +444,20 @@ def test_kappa_zero_is_identity(pkg):
     c.close()
 
 
-@pytest.mark.parametrize("n", [(0, 0, 0, 0), (1, 0, 2, 1), (3, 1, 1, 5)])
-def test_free_field_plane_wave(pkg, n):
+@pytest.mark.parametrize("n,bc_t", [((0, 0, 0, 0), 0), ((1, 0, 2, 1), 0), ((3, 1, 1, 5), 0),
+                                    ((0, 0, 0, 0), 1), ((2, 1, 0, 3), 1)])
+def test_free_field_plane_wave(pkg, n, bc_t):
     """Unit links: A e^{ipx} u = [1 - 2 kappa sum cos p_mu + 2 i kappa sum gamma_mu sin p_mu] e^{ipx} u
-    with p_mu = 2 pi n_mu / L_mu (periodic), checked on the GPU against the closed form."""
+    with p_mu = 2 pi n_mu / L_mu, and p_t = pi (2 n_t + 1) / L_t for antiperiodic time, checked on
+    the GPU against the closed form."""
     from oracle import gammas
     dims = (4, 3, 4, 6)
     V = wi.volume(dims)
     kappa = 0.11
     U = np.zeros((4, V, 3, 3), dtype=np.complex128)
     U[:, :] = np.eye(3)
-    c = _ctx(pkg, dims, U, kappa, 1.3, 0)
-    p = [2 * np.pi * n[m] / dims[m] for m in range(4)]
+    c = _ctx(pkg, dims, U, kappa, 1.3, bc_t)
+    p = [2 * np.pi * n[m] / dims[m] for m in range(3)] + [np.pi * (2 * n[3] + bc_t) / dims[3]]
     s = np.arange(V)
     x = [s % dims[0], (s // dims[0]) % dims[1], (s // (dims[0] * dims[1])) % dims[2], s // (dims[0] * dims[1] * dims[2])]
     phase = np.exp(1j * sum(p[m] * x[m] for m in range(4)))            # (V,)
