@@ -471,3 +471,38 @@ def test_free_field_plane_wave(pkg, n, bc_t):
     Y = _host(c.apply(_dev(B)))
     assert _maxrel(Y, expect) < 1e-13
     c.close()
+
+
+@pytest.mark.parametrize("bc_t", [0, 1])
+def test_gauge_covariance_on_gpu(pkg, bc_t):
+    """A[U^g](g psi) = g A[U] psi with U^g_mu(x) = g(x) U_mu(x) g(x + mu)^dag, both sides on the GPU
+    (the links, clover and T^-1 are rebuilt from U^g), and the same for one Jacobi application."""
+    dims = (4, 6, 2, 4)
+    V = wi.volume(dims)
+    lx, ly, lz, lt = dims
+    U = wi.random_links(dims, 0.5, 160)
+    gx = wi.random_gauge_transform(dims, 1.0, 161)
+    s = np.arange(V)
+    co = [s % lx, (s // lx) % ly, (s // (lx * ly)) % lz, s // (lx * ly * lz)]
+    Ug = np.empty_like(U)
+    for mu in range(4):
+        c = [a.copy() for a in co]
+        c[mu] = (c[mu] + 1) % dims[mu]
+        s2 = c[0] + lx * (c[1] + ly * (c[2] + lz * c[3]))
+        Ug[mu] = gx @ U[mu] @ np.conj(np.transpose(gx[s2], (0, 2, 1)))
+    c1 = _ctx(pkg, dims, U, 0.125, 1.3, bc_t)
+    c2 = _ctx(pkg, dims, Ug, 0.125, 1.3, bc_t)
+    psi = wi.gaussian_block(V, 3, 162)                                   # (L, 12, V)
+
+    def gmul(b):                                                         # colour rotation per site
+        f = b.reshape(b.shape[0], 4, 3, V)
+        return np.einsum("vab,lsbv->lsav", gx, f).reshape(b.shape)
+
+    lhs = _host(c2.apply(_dev(gmul(psi))))
+    rhs = gmul(_host(c1.apply(_dev(psi))))
+    assert _maxrel(lhs, rhs) < 1e-13
+    lhs = _host(c2.jacobi(_dev(gmul(psi)), 4))
+    rhs = gmul(_host(c1.jacobi(_dev(psi), 4)))
+    assert _maxrel(lhs, rhs) < 1e-13
+    c1.close()
+    c2.close()
