@@ -506,3 +506,43 @@ def test_gauge_covariance_on_gpu(pkg, bc_t):
     assert _maxrel(lhs, rhs) < 1e-13
     c1.close()
     c2.close()
+
+
+def test_single_link_clover_closed_form_on_gpu(pkg):
+    """All links 1 except U_x(x0) = diag(e^{i phi}, e^{-i phi}, 1): the GPU clover equals the
+    hand-derived T = 1 - kappa c_SW sigma_{x nu} F_{x nu}, F_{x nu} = +-(sin phi / 4) diag(1, -1, 0)
+    at x0 +- nu and x0 + x +- nu, and 1 everywhere else (sigma_{x nu} = -diag(s3, s3),
+    diag(s2, s2), diag(s1, -s1) for nu = y, z, t in the chiral basis)."""
+    dims = (4, 4, 4, 4)
+    V = wi.volume(dims)
+    phi, kappa, csw = 0.7, 0.13, 1.9
+    x0 = (1, 2, 1, 3)
+
+    def site(c):
+        c = [c[m] % dims[m] for m in range(4)]
+        return c[0] + 4 * (c[1] + 4 * (c[2] + 4 * c[3]))
+
+    U = np.zeros((4, V, 3, 3), dtype=np.complex128)
+    U[...] = np.eye(3)
+    U[0, site(x0)] = np.diag([np.exp(1j * phi), np.exp(-1j * phi), 1.0])
+    c = _ctx(pkg, dims, U, kappa, csw, 0)
+    T = c.clover(0)                                                      # (V, 2, 6, 6)
+    c.close()
+    f = np.sin(phi) / 4 * np.diag([1.0, -1.0, 0.0])
+    s1 = np.array([[0, 1], [1, 0]])
+    s2 = np.array([[0, -1j], [1j, 0]])
+    s3 = np.array([[1, 0], [0, -1]])
+    z2 = np.zeros((2, 2))
+    sig = {1: -np.block([[s3, z2], [z2, s3]]), 2: np.block([[s2, z2], [z2, s2]]), 3: np.block([[s1, z2], [z2, -s1]])}
+    expected = np.tile(np.eye(12, dtype=complex), (V, 1, 1))
+    for nu in (1, 2, 3):
+        for sign in (+1, -1):
+            cc = list(x0)
+            cc[nu] += sign
+            for shift in (0, 1):
+                c2 = list(cc)
+                c2[0] += shift
+                expected[site(c2)] -= kappa * csw * sign * np.kron(sig[nu], f)
+    assert np.max(np.abs(expected[:, :6, 6:])) == 0 and np.max(np.abs(expected[:, 6:, :6])) == 0
+    assert np.max(np.abs(T[:, 0] - expected[:, :6, :6])) < 1e-14
+    assert np.max(np.abs(T[:, 1] - expected[:, 6:, 6:])) < 1e-14
