@@ -125,6 +125,26 @@ def time_hop(ctx, torch, V, L, mode, reps, prec="f64"):
     return (t[1] - t[0]) / reps
 
 
+def time_copy(torch, V, L, reps=5):
+    """Device-to-device copy of one N x L block with torch (read + write bytes per second): the
+    rate a plain streaming kernel reaches on this GPU, reported beside the roofline."""
+    a = torch.empty((L, 12, V), dtype=torch.complex128, device="cuda")
+    b = torch.empty_like(a)
+    a.fill_(1.0)
+    b.copy_(a)
+    torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        b.copy_(a)
+    e1.record()
+    e1.synchronize()
+    ms = e0.elapsed_time(e1) / reps
+    del a, b
+    return 2 * L * 12 * V * 16 / (ms / 1e3) / 1e9
+
+
 def solve_record(info, L, X=None, Xref=None, torch=None, np=None):
     d = {"status": info["status"], "iterations": info["total_iterations"], "cycles": info["cycles"],
          "fallback": info["fallback"], "s_per_rhs": round(info["seconds"] / L, 5),
@@ -416,9 +436,11 @@ def main():
     b_sweep = V * (1152 + 576 * L)
     b_apply = V * (1152 + 384 * L)
     ach = b_sweep / (ms_sweep / 1e3) / 1e9
+    copy_gbs = time_copy(torch, V, L)
     roof = {"bound": "hbm", "achieved": round(ach, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": round(ach / HBM_PEAK_GBS, 4), "traffic": traffic_from_profiles(1),
             "kernel": f"k_hop<StF64,StF64,CT,JBLOCK> (Jacobi sweep, L={L})",
+            "copy_GBs": round(copy_gbs, 1), "frac_of_copy": round(ach / copy_gbs, 4),
             "avg_launch_ms": round(ms_sweep, 4), "alg_bytes_per_launch": b_sweep}
     ach_a = b_apply / (ms_apply / 1e3) / 1e9
     dslash = {"achieved": round(ach_a, 1), "frac": round(ach_a / HBM_PEAK_GBS, 4), "unit": "GB/s",
