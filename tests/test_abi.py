@@ -110,3 +110,19 @@ def test_struct_layouts_match_header():
         fields = re.findall(r"(\w+)(?:\[\w+\])?\s*;", body)
         assert fields == [f for f, _ in cls._fields_]
     assert ctypes.sizeof(SolveInfo) == 7 * 4 + 4 + 8 * 2 + 8 + 8 + 2 * 16 * 8
+
+
+def test_binding_constants_match_header():
+    """Every #define of the header that the binding also names has the same value there."""
+    from paper_0907_3261_amd import _binding as b
+    text = open(HEADER).read()
+    defines = dict(re.findall(r"^#define (WD_\w+)\s+\(?(-?\d+)\)?", text, flags=re.M))
+    shared = [n for n in defines if hasattr(b, n)]
+    for must in ("WD_F64", "WD_F32", "WD_BF16", "WD_F64_COEF_F32", "WD_F64_COEF_BF16", "WD_MAX_L",
+                 "WD_PRECOND_LEARNED", "WD_EINVAL", "WD_STAGNATED"):
+        assert must in shared, must
+    for n in shared:
+        assert getattr(b, n) == int(defines[n]), n
+    # the precision names of the binding map onto header constants
+    assert set(b.PREC.values()) == {int(defines[n]) for n in
+                                    ("WD_F64", "WD_F32", "WD_BF16", "WD_F64_COEF_F32", "WD_F64_COEF_BF16")}
