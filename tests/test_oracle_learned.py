@@ -133,3 +133,28 @@ def test_site_layer_matches_field_layer(bc_t):
     for s in range(op.V):
         got = ln.layer_at(so, W, s, lambda t: b[:, :, t].T)
         assert np.max(np.abs(got - ref[:, :, s].T)) < 1e-14
+
+
+def test_adam_closed_form_steps():
+    """Adam with bias correction, from its definition (not from the oracle's code): with a
+    constant gradient the bias-corrected first and second moments equal g and g^2, so every
+    step moves each real component by lr * g / (|g| + eps), i.e. lr * sign(g); with the
+    gradient alternating g, -g the second step's corrected moments are
+    m_hat = (0.9 * 0.1 - 0.1) g / (1 - 0.9^2) = -g / 19 and v_hat = g^2, a move of
+    +lr / 19 * sign(g).  Real and imaginary parts are separate parameters."""
+    lr = 1e-2
+    g = np.array([[0.5 - 2.0j, -3.0 + 0.25j]])
+    th0 = np.zeros_like(g)
+    sign = np.sign(g.real) + 1j * np.sign(g.imag)
+    # constant gradient: two steps of lr * sign(g) each (eps = 1e-8 is below 1e-7 relative here)
+    st = {}
+    th1 = ln.adam(th0, g, st, lr=lr)
+    assert np.max(np.abs(th1 - (th0 - lr * sign))) < 1e-9
+    th2 = ln.adam(th1, g, st, lr=lr)
+    assert np.max(np.abs(th2 - (th0 - 2 * lr * sign))) < 1e-9
+    # alternating gradient
+    st = {}
+    t1 = ln.adam(th0, g, st, lr=lr)
+    t2 = ln.adam(t1, -g, st, lr=lr)
+    assert np.max(np.abs((t2 - t1) - lr / 19.0 * sign)) < 1e-9
+    assert st["t"] == 2

@@ -304,3 +304,29 @@ def test_layout_roundtrip_and_point_source():
     pb = wi.point_block(op.V, 12)
     pm = op.block_to_mat(pb)
     assert np.array_equal(pm, np.eye(op.N, 12))
+
+
+# ------------------------------------------------- site-by-site operator
+
+@pytest.mark.parametrize("dims,bc_t", [((3, 5, 3, 5), 0), ((3, 5, 3, 5), 1), ((2, 2, 2, 2), 0),
+                                       ((2, 2, 2, 2), 1)])
+def test_site_operator_matches_field_operator(dims, bc_t):
+    """SiteOperator (used for the full-size spot checks on the GPU) builds T from its own
+    link-by-link leaves and the hop from kron((1 -+ g_mu), U) products; at every site of an
+    odd-extent lattice and of 2^4 (where x + mu = x - mu and both hops add) its T, hop and
+    A psi equal the field operator's, which the closed forms above pin."""
+    from oracle.dirac import SiteOperator
+    U = wi.random_links(dims, 0.4, 31 + bc_t)
+    kappa, csw = 0.124, 1.3
+    op = WilsonClover(dims, U, kappa, csw, bc_t=bc_t)
+    so = SiteOperator(dims, U, kappa, csw, bc_t)
+    b = wi.gaussian_block(op.V, 3, 17)
+    f = op.from_block(b)
+    H = op.to_block(op.hop(f))
+    A = op.to_block(op.apply_A(f))
+    T = op.T.reshape(op.V, 12, 12)   # oracle field order is [t, z, y, x] = site order
+    get = lambda s: b[:, :, s].T      # (12, L) at site s
+    for s in range(op.V):
+        assert np.max(np.abs(so.T(s) - T[s])) < 1e-15
+        assert _rel(so.hop_at(s, get), H[:, :, s].T) < 1e-14
+        assert _rel(so.apply_at(s, get), A[:, :, s].T) < 1e-14
