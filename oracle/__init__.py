@@ -20,6 +20,9 @@ Contents (each function cites the passage it follows):
                  algorithm box), written as the paper's closed-form sum.
 * ``bbicggr`` -- preconditioned block BiCGGR (Sec. 2, algorithm box), step
                  by step, with the stopping rule of Sec. 3.3.
+* ``bicgstab`` -- preconditioned block BiCGSTAB (the published block
+                 version of BiCGSTAB), the foil whose recursive residual drifts
+                 from the true one, which BiCGGR is built to avoid (Sec. 1).
 * ``learned`` -- the linear gauge-covariant network layers used as an
                  alternative preconditioner: forward, adjoint, weight
                  gradients.
@@ -31,7 +34,8 @@ hopping-parameter form of the O(a)-improved Wilson-Dirac matrix, stated in
 clover field), gamma5-hermiticity, gauge covariance and dense-matrix checks.
 """
 
-from . import dirac, jacobi, bbicggr  # noqa: F401
+from . import dirac, jacobi, bbicggr, bicgstab  # noqa: F401
 from .dirac import WilsonClover, gammas, gamma5, sigma_munu  # noqa: F401
 from .jacobi import jacobi_apply  # noqa: F401
 from .bbicggr import block_bicggr, solve_with_restarts  # noqa: F401
+from .bicgstab import block_bicgstab  # noqa: F401

@@ -239,3 +239,50 @@ def test_restart_from_solution_is_immediate():
     X2, info2 = solve_with_restarts(op.A_mat, lambda m: jacobi_mat(op, m, 2), B, 1e-12, 2)
     assert info2["status"] == "converged"
     assert np.max(info2["true_residual"]) <= 1e-12
+
+
+# ---------------------------------------------------------------- block BiCGSTAB (the foil)
+
+from oracle.bicgstab import block_bicgstab  # noqa: E402
+
+
+@pytest.mark.parametrize("j", [0, 2])
+def test_bicgstab_single_column_matches_scipy(j):
+    """L = 1: the block recurrences reduce to van der Vorst's BiCGSTAB; scipy's
+    right-preconditioned implementation (r~ = r_0, x += alpha M p + omega M s) must produce the
+    same iterates, which pins alpha, omega and the block form of beta."""
+    import scipy.sparse.linalg as sla
+    op = _op(dims=(2, 2, 4, 4), kappa=0.12, csw=1.1)
+    N = op.N
+    b = op.block_to_mat(wi.z4_block(op.V, 1, 41))
+    Mf = (lambda m: jacobi_mat(op, m, j)) if j else (lambda m: m)
+    Aop = sla.LinearOperator((N, N), matvec=lambda v: op.A_mat(v.reshape(N, 1))[:, 0], dtype=np.complex128)
+    Mop = sla.LinearOperator((N, N), matvec=lambda v: Mf(v.reshape(N, 1))[:, 0], dtype=np.complex128)
+    xs = []
+    sla.bicgstab(Aop, b[:, 0], M=Mop, rtol=1e-30, atol=0.0, maxiter=8, callback=lambda x: xs.append(x.copy()))
+    mine = []
+    block_bicgstab(op.A_mat, Mf, b, 1e-30, j, max_iter=8, callback=lambda d: mine.append(d["X"][:, 0].copy()))
+    assert len(xs) == 8 and len(mine) == 8
+    for a, c in zip(mine, xs):
+        assert np.linalg.norm(a - c) / np.linalg.norm(c) < 1e-11
+
+
+@pytest.mark.parametrize("j,L", [(0, 3), (2, 2)])
+def test_bicgstab_matches_dense_lu(j, L):
+    op = _op(kappa=0.12, csw=1.2, eps=0.4)
+    B = op.block_to_mat(wi.z4_block(op.V, L, 42))
+    X, info = block_bicgstab(op.A_mat, lambda m: jacobi_mat(op, m, j), B, 1e-12, j)
+    assert info["status"] == "converged"
+    assert info["mvm_paper"] == 2 * (j + 1) * info["iterations"] + 1
+    Xd = np.linalg.solve(op.dense(), B)
+    cond = np.linalg.cond(op.dense())
+    assert np.linalg.norm(X - Xd) / np.linalg.norm(Xd) < cond * 1e-11
+
+
+def test_bicgstab_exact_preconditioner_one_iteration():
+    op = _op(kappa=0.13, csw=1.2)
+    Ainv = np.linalg.inv(op.dense())
+    B = op.block_to_mat(wi.z4_block(op.V, 3, 43))
+    X, info = block_bicgstab(op.A_mat, lambda m: Ainv @ m, B, 1e-12, 0)
+    assert info["status"] == "converged" and info["iterations"] == 1
+    assert np.linalg.norm(X - Ainv @ B) / np.linalg.norm(X) < 1e-13
