@@ -42,8 +42,10 @@
  *
  * Errors: 0 is success; negative values are API or runtime errors (nothing
  *   is modified on argument errors); positive values are numerical outcomes
- *   of the solver, which still returns its best iterate.  No C++ exception
- *   or abort crosses this interface.
+ *   of the solver, which still returns an iterate: the last one when
+ *   max_iter is reached, otherwise the run's recovery point or, after a
+ *   breakdown, the iterate it stopped on.  No C++ exception or abort crosses
+ *   this interface.
  */
 #ifndef WDSOLVE_H
 #define WDSOLVE_H
@@ -118,11 +120,29 @@ typedef struct wd_solve_opts {
                               training pairs of the learned preconditioner (wd_learned_pairs) */
     int snap_count;        /* slots in x_snap (0: no snapshots) */
     int snap_every;        /* iterations between snapshots (>= 1 when snap_count > 0) */
+    double* gap_history;   /* optional host buffer of history_len doubles: per outer iteration, the
+                              largest per-column ||r_k - (b - A x_k)|| / ||b|| between the recursive
+                              and the true residual (a diagnostic: one more application of A per
+                              iteration) */
+    double* cond_history;  /* optional host buffer of history_len doubles: per outer iteration, the
+                              larger condition estimate (largest over smallest LU pivot modulus) of
+                              the L x L matrices Rt_0^H V_k and Rt_0^H R_k (block BiCGSTAB: Rt_0^H V_k) */
+    double cond_limit;     /* > 0: a condition estimate above this ends the run as a breakdown (rank
+                              loss of the block); 0 or less: only singular systems do */
+    int no_split;          /* block BiCGGR, FP64 runs: 0 (default) -- when a run of L > 1 columns breaks
+                              down, diverges or stagnates, X returns to its recovery point (the last
+                              iterate that had cut the largest residual tenfold) and the two halves
+                              of the block are solved as blocks of their own, recursively: the remedy
+                              of Sec. 3.3, a smaller L; 1 -- no splitting (a failed run of L = 1
+                              columns, or with splitting off, restarts from its recovery point while
+                              max_restarts allows) */
 } wd_solve_opts;
 
 /* Results of bbicggr_solve. */
 typedef struct wd_solve_info {
-    int status;                        /* WD_OK or a positive outcome code */
+    int status;                        /* the code the call returned: WD_OK, a positive outcome code, or a
+                                          negative error met during the solve (e.g. WD_ENAN, WD_EHIP); the
+                                          other fields then describe the work done until then */
     int iterations;                    /* outer iterations of the last run */
     int total_iterations;              /* over all restarts */
     int restarts;                      /* true-residual restarts made */
@@ -135,6 +155,9 @@ typedef struct wd_solve_info {
     double bytes_alg;                  /* algorithmic HBM bytes of every kernel launched by the solve */
     double true_residual[WD_MAX_L];    /* ||b - A x|| / ||b|| per column, FP64 */
     double recursive_residual[WD_MAX_L];
+    double cond_max;                   /* largest condition estimate of the L x L systems over all runs */
+    int splits;                        /* block splits made after failed runs */
+    int min_block;                     /* smallest block width solved */
 } wd_solve_info;
 
 /* ---------------------------------------------------------------------------
@@ -197,10 +220,30 @@ int jacobi_precond(wd_ctx* ctx, const void* R, void* Z, int L, int j, int prec);
  * then recomputed and the solver restarts from the current X while any
  * column's true residual exceeds tol (up to max_restarts times).  B and X are
  * device block vectors (X in/out); opts may be NULL (defaults, j = 0); info
- * may be NULL.  Every column of B must be non-zero.
+ * may be NULL and is filled on every return after the arguments were
+ * accepted.  Every column of B must be non-zero.  A run that breaks down,
+ * diverges or stagnates is continued on the two halves of its block (see
+ * no_split), following the advice of Sec. 3.3 to repeat the inversion with
+ * smaller L.
  * Returns WD_OK, a positive outcome code, or a negative error. */
 int bbicggr_solve(wd_ctx* ctx, const void* B, void* X, int L, double tol,
                   const wd_solve_opts* opts, wd_solve_info* info);
+
+/* Solve A X = B with preconditioned block BiCGSTAB: the published block
+ * version of BiCGSTAB (Guennouni, Jbilou and Sadok, ETNA 16, 2003) with M on
+ * the right, the method whose recursive residual drifts from the true one,
+ * which block BiCGGR avoids (Sec. 1).  Per iteration, with Rt_0 = R_0:
+ *   Ph = M P, V = A Ph, (Rt_0^H V) alpha = Rt_0^H R, S = R - V alpha,
+ *   Sh = M S, T = A Sh, omega = Tr[T^H S] / Tr[T^H T],
+ *   X += Ph alpha + omega Sh, R = S - omega T,
+ *   (Rt_0^H V) beta = -Rt_0^H T, P = R + (P - omega V) beta.
+ * Same arguments, stopping rule, true-residual restarts and cost count as
+ * bbicggr_solve; of the options it takes j, precond (WD_PRECOND_NONE or
+ * WD_PRECOND_JACOBI with prec_inner WD_F64), use_x0, max_iter, max_restarts,
+ * stagnate_window, diverge_at, history, gap_history, cond_history and
+ * cond_limit (no cycles, fallback, snapshots or splitting). */
+int bbicgstab_solve(wd_ctx* ctx, const void* B, void* X, int L, double tol,
+                    const wd_solve_opts* opts, wd_solve_info* info);
 
 /* Throughput measurement: launch the hopping kernel nrep times back to back
  * on the context stream, then wait.  mode 0 is Y = A X (as wd_apply);

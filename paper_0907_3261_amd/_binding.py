@@ -49,7 +49,8 @@ class SolveOpts(ctypes.Structure):
                 ("max_iter", c_int), ("max_restarts", c_int), ("stagnate_window", c_int),
                 ("diverge_at", c_double), ("history", POINTER(c_double)), ("history_len", c_int),
                 ("cycle_tol", c_double), ("no_fallback", c_int), ("x_snap", c_void_p), ("snap_count", c_int),
-                ("snap_every", c_int)]
+                ("snap_every", c_int), ("gap_history", POINTER(c_double)), ("cond_history", POINTER(c_double)),
+                ("cond_limit", c_double), ("no_split", c_int)]
 
 
 class SolveInfo(ctypes.Structure):
@@ -57,7 +58,8 @@ class SolveInfo(ctypes.Structure):
                 ("cycles", c_int), ("fallback", c_int), ("snapshots", c_int),
                 ("mvm_paper", c_longlong), ("mvm_actual", c_longlong), ("seconds", c_double),
                 ("bytes_alg", c_double),
-                ("true_residual", c_double * WD_MAX_L), ("recursive_residual", c_double * WD_MAX_L)]
+                ("true_residual", c_double * WD_MAX_L), ("recursive_residual", c_double * WD_MAX_L),
+                ("cond_max", c_double), ("splits", c_int), ("min_block", c_int)]
 
 
 class WDError(RuntimeError):
@@ -77,6 +79,8 @@ SIGNATURES = [
     ("jacobi_precond", c_int, [c_void_p, c_void_p, c_void_p, c_int, c_int, c_int]),
     ("bbicggr_solve", c_int, [c_void_p, c_void_p, c_void_p, c_int, c_double, POINTER(SolveOpts),
                               POINTER(SolveInfo)]),
+    ("bbicgstab_solve", c_int, [c_void_p, c_void_p, c_void_p, c_int, c_double, POINTER(SolveOpts),
+                                POINTER(SolveInfo)]),
     ("wd_hop_repeat", c_int, [c_void_p, c_void_p, c_void_p, c_void_p, c_int, c_int, c_int, c_int]),
     ("wd_block_gram", c_int, [c_void_p, c_void_p, c_void_p, c_int, c_void_p]),
     ("wd_small_solve", c_int, [c_void_p, c_void_p, c_void_p, c_int, c_void_p]),
@@ -230,15 +234,22 @@ class Context:
     def solve(self, B, X=None, tol: float = 1e-12, j: int = 0, precond: int | None = None,
               prec_inner: str = "f64", max_iter: int = 0, max_restarts: int = -1, diverge_at: float = 0.0,
               stagnate_window: int = 0, history_len: int = 0, cycle_tol: float = 0.0,
-              no_fallback: bool = False, x_snap=None, snap_every: int = 0):
-        """Preconditioned block BiCGGR; returns (X, info dict).  X, if given, is the initial guess."""
+              no_fallback: bool = False, x_snap=None, snap_every: int = 0, gap_history: bool = False,
+              cond_history: bool = False, cond_limit: float = 0.0, no_split: bool = False,
+              method: str = "bicggr"):
+        """Preconditioned block BiCGGR (method "bicggr") or the block BiCGSTAB foil ("bicgstab");
+        returns (X, info dict).  X, if given, is the initial guess.  gap_history / cond_history
+        ask for the per-iteration residual gap and condition estimate (history_len entries)."""
         L = B.shape[0]
         use_x0 = X is not None
         if X is None:
             X = self.empty_block(L)
         if precond is None:
             precond = WD_PRECOND_JACOBI if j > 0 else WD_PRECOND_NONE
-        hist = (c_double * max(history_len, 1))()
+        n_hist = max(history_len, 1)
+        hist = (c_double * n_hist)()
+        ghist = (c_double * n_hist)()
+        chist = (c_double * n_hist)()
         o = SolveOpts(j=int(j), precond=int(precond), prec_inner=PREC[prec_inner], use_x0=int(use_x0),
                       max_iter=int(max_iter), max_restarts=int(max_restarts),
                       stagnate_window=int(stagnate_window), diverge_at=float(diverge_at),
@@ -246,19 +257,31 @@ class Context:
                       history_len=int(history_len), cycle_tol=float(cycle_tol),
                       no_fallback=int(bool(no_fallback)),
                       x_snap=self._snap_ptr(x_snap, L), snap_count=(x_snap.shape[0] // L) if x_snap is not None else 0,
-                      snap_every=int(snap_every))
+                      snap_every=int(snap_every),
+                      gap_history=ctypes.cast(ghist, POINTER(c_double)) if (history_len and gap_history) else None,
+                      cond_history=ctypes.cast(chist, POINTER(c_double)) if (history_len and cond_history) else None,
+                      cond_limit=float(cond_limit), no_split=int(bool(no_split)))
         info = SolveInfo()
-        code = _check(self._lib.bbicggr_solve(self._h, self._block(B), self._block(X, L), L, float(tol),
-                                              ctypes.byref(o), ctypes.byref(info)), "bbicggr_solve")
-        d = dict(code=code, status=STATUS_NAME.get(code, str(code)), iterations=info.iterations,
+        fn = {"bicggr": self._lib.bbicggr_solve, "bicgstab": self._lib.bbicgstab_solve}[method]
+        code = fn(self._h, self._block(B), self._block(X, L), L, float(tol), ctypes.byref(o), ctypes.byref(info))
+        if code != WD_ENAN:          # a non-finite residual is an outcome of the solve, reported in info
+            _check(code, method)
+        d = dict(code=code, status=STATUS_NAME.get(code, str(code)), info_status=info.status,
+                 iterations=info.iterations,
                  total_iterations=info.total_iterations, restarts=info.restarts, cycles=info.cycles,
                  fallback=bool(info.fallback), snapshots=info.snapshots,
                  mvm_paper=info.mvm_paper,
                  mvm_actual=info.mvm_actual, seconds=info.seconds, bytes_alg=info.bytes_alg,
                  true_residual=np.array(info.true_residual[:L]),
-                 recursive_residual=np.array(info.recursive_residual[:L]))
+                 recursive_residual=np.array(info.recursive_residual[:L]),
+                 cond_max=info.cond_max, splits=info.splits, min_block=info.min_block)
         if history_len:
-            d["history"] = np.array(hist[:min(history_len, info.total_iterations + info.cycles + info.restarts)])
+            n = min(history_len, info.total_iterations + info.cycles)
+            d["history"] = np.array(hist[:n])
+            if gap_history:
+                d["gap_history"] = np.array(ghist[:n])
+            if cond_history:
+                d["cond_history"] = np.array(chist[:n])
         return X, d
 
     def hop_repeat(self, X, Y, nrep: int, mode: int = 0, R=None, prec: str = "f64"):

@@ -55,26 +55,30 @@ enum { WS_R = 0, WS_RT, WS_P, WS_V, WS_W, WS_F, WS_G, WS_U, WS_Y, WS_T1, WS_JT =
 // Small device control block (after the L x L matrices in ctx->small)
 struct Ctl {
     double norms[WD_MAX_L];
+    double cond[2];  // condition estimates of the two L x L systems of the last iteration
     int status;
     int pad;
 };
 
+// ctx->small: eight L x L matrices (256 pairs each), 16 scalars, the control block
 struct SmallLayout {
+    double2* mats[8];
     double2 *C_r, *C_rn, *alpha, *gamma, *zeta;
     Ctl* ctl;
 };
 
 SmallLayout small_layout(wd_ctx* c) {
     SmallLayout s;
-    s.C_r = c->small;
-    s.C_rn = c->small + 256;
-    s.alpha = c->small + 512;
-    s.gamma = c->small + 768;
-    s.zeta = c->small + 1024;
-    s.ctl = reinterpret_cast<Ctl*>(c->small + 1032);
+    for (int i = 0; i < 8; ++i) s.mats[i] = c->small + 256 * i;
+    s.C_r = s.mats[0];
+    s.C_rn = s.mats[1];
+    s.alpha = s.mats[2];
+    s.gamma = s.mats[3];
+    s.zeta = c->small + 2048;
+    s.ctl = reinterpret_cast<Ctl*>(c->small + 2064);
     return s;
 }
-constexpr size_t kSmallPairs = 1032 + (sizeof(Ctl) + 15) / 16 + 1;
+constexpr size_t kSmallPairs = 2064 + (sizeof(Ctl) + 15) / 16 + 1;
 
 int check_prec(int prec) { return (prec == WD_F64 || prec == WD_F32 || prec == WD_BF16) ? WD_OK : WD_EINVAL; }
 // the Jacobi preconditioner also takes FP64 iterates with low-precision coefficients
@@ -396,13 +400,14 @@ int wd_learned_pairs(wd_ctx* c, const void* B, const void* X, const void* Xsnap,
 }
 
 // ---------------------------------------------------------------------------
-// Preconditioned block BiCGGR
+// Preconditioned block BiCGGR (and the block BiCGSTAB foil)
 // ---------------------------------------------------------------------------
 namespace {
 
 struct Solver {
     wd_ctx* c;
-    int L;
+    int L;      // width of the block being solved
+    int Ltot;   // columns of the whole solve
     size_t N;
     int nb;
     int j;
@@ -411,8 +416,8 @@ struct Solver {
     int coef = 0;  // Jacobi with FP64 iterates: 0, or the storage (Prec) of its links and A_D^{-1}
     SmallLayout sl;
     SolverBufs bufs;
-    long long mvm_paper = 0, mvm_actual = 0;
-    double bytes = 0.0;  // algorithmic HBM bytes of the launched kernels
+    long long mvm_paper = 0, mvm_actual = 0;  // operator applications, summed over columns
+    double bytes = 0.0;                       // algorithmic HBM bytes of the launched kernels
 
     double2* ws(int i) { return c->ws[i]; }
     // one pass over n N x L blocks
@@ -420,8 +425,10 @@ struct Solver {
 
     int applyM(const double2* in, double2* out) {
         if (precond == WD_PRECOND_LEARNED) {
-            WD_TRY_HIP(launch_learned(c, in, out, L, pin, c->ws[WS_JT], c->ws[WS_T2], c->stream));
-            mvm_actual += WD_LEARNED_LAYERS;
+            // scratch: the Jacobi temporary and T1, both idle while M is applied (the recovery
+            // point and a cycle's best iterate live in T2)
+            WD_TRY_HIP(launch_learned(c, in, out, L, pin, c->ws[WS_JT], c->ws[WS_T1], c->stream));
+            mvm_actual += (long long)WD_LEARNED_LAYERS * L;
             // three layers: links read once per site, one input and one output block each
             // (FP32: 288 + 192 L B per site, with the first input and last output in FP64)
             bytes += pin == Prec::F64 ? (double)c->g.V * 3 * (576.0 + 384.0 * L)
@@ -430,34 +437,45 @@ struct Solver {
         }
         if (precond == WD_PRECOND_JACOBI && j > 0 && coef) {
             WD_TRY_HIP(launch_jacobi_coef(c, in, out, L, j, (Prec)coef, c->stream));
-            mvm_actual += j - 1;
+            mvm_actual += (long long)(j - 1) * L;
             // FP64 vectors; links (576 B per site in FP64) and A_D^{-1} (576 B) at 1/2 or 1/4
             const double cs = coef == (int)Prec::F32 ? 0.5 : 0.25;
             bytes += (double)c->g.V * (bytes_first_sweep(L) - 576.0 * (1.0 - cs) +
                                        (j - 1) * (bytes_sweep(L) - 1152.0 * (1.0 - cs)));
         } else if (precond == WD_PRECOND_JACOBI && j > 0) {
             WD_TRY_HIP(launch_jacobi(c, in, out, L, j, pin, c->stream));
-            mvm_actual += j - 1;
+            mvm_actual += (long long)(j - 1) * L;
             const double scale = pin == Prec::F64 ? 1.0 : (pin == Prec::F32 ? 0.5 : 0.25);
             bytes += (double)c->g.V * (bytes_first_sweep(L) + (j - 1) * bytes_sweep(L)) * scale;
         } else {
             WD_TRY_HIP(launch_copy(out, in, N * L, c->stream));
             blocks(2);
         }
-        mvm_paper += j;
+        mvm_paper += (long long)j * L;
         return WD_OK;
     }
-    int applyA(const double2* in, double2* out) {
+    int applyA(const double2* in, double2* out, bool paper = true) {
         WD_TRY_HIP(launch_apply_A(c, in, out, L, c->stream));
-        mvm_paper += 1;
-        mvm_actual += 1;
+        if (paper) mvm_paper += L;
+        mvm_actual += L;
         bytes += (double)c->g.V * bytes_apply(L);
         return WD_OK;
     }
     int gram_into(const double2* P, const double2* Q, double2* C) {
         WD_TRY_HIP(launch_gram_partials(P, Q, N, L, c->partial, nb, c->stream));
         WD_TRY_HIP(launch_reduce_gram(c->partial, nb, L, C, c->stream));
+        blocks(2);
         return WD_OK;
+    }
+    int copy(double2* dst, const double2* src) {
+        WD_TRY_HIP(launch_copy(dst, src, N * L, c->stream));
+        blocks(2);
+        return WD_OK;
+    }
+    // squared column norms of an N x L block, on the host (synchronises)
+    int norms(const double2* Rb, double* out) {
+        blocks(1);
+        return colnorms_host(c, Rb, L, out);
     }
     int fetch_ctl(Ctl* h) {
         WD_TRY_HIP(hipMemcpyAsync(h, sl.ctl, sizeof(Ctl), hipMemcpyDeviceToHost, c->stream));
@@ -466,139 +484,135 @@ struct Solver {
     }
 };
 
-}  // namespace
-
-int bbicggr_solve(wd_ctx* c, const void* Bv, void* Xv, int L, double tol, const wd_solve_opts* o,
-                  wd_solve_info* info) {
-    if (!c || !Bv || !Xv) return WD_EINVAL;
-    if (L < 1 || L > c->max_L || !(tol > 0.0)) return WD_EINVAL;
-    if (!c->have_params) return WD_ESTATE;
-    wd_solve_opts op{};
-    if (o) op = *o;
-    if (op.precond != WD_PRECOND_NONE && op.precond != WD_PRECOND_JACOBI && op.precond != WD_PRECOND_LEARNED)
-        return WD_EINVAL;
-    if (op.j < 0 || (check_prec(op.prec_inner) && !coef_prec(op.prec_inner))) return WD_EINVAL;
-    if (op.snap_count < 0 || (op.snap_count > 0 && (!op.x_snap || op.snap_every < 1))) return WD_EINVAL;
-    if (op.precond == WD_PRECOND_LEARNED) {
-        if (op.prec_inner == WD_BF16 || coef_prec(op.prec_inner)) return WD_EINVAL;
-        if (!c->have_theta) return WD_ESTATE;
-        int r0 = learned_ensure(c);
-        if (r0) return r0;
-    }
-    // FP64 fallback for an inexact M whose cycles stall: Jacobi in FP64 with the caller's j (M = I if 0)
-    const int fb_j = op.j;
-    if (op.precond != WD_PRECOND_JACOBI) op.j = 0;
-    const int max_iter = op.max_iter > 0 ? op.max_iter : 5000;
-    const int max_restarts = op.max_restarts >= 0 ? op.max_restarts : 3;
-    const int stag = op.stagnate_window > 0 ? op.stagnate_window : 200;
-    const double diverge_at = op.diverge_at > 0 ? op.diverge_at : 1e2;
-    const size_t N = (size_t)12 * c->g.V;
-    if (overlap(Bv, Xv, N * L * 16)) return WD_EINVAL;
-    const size_t blk_bytes = N * L * 16;
-    if (op.snap_count > 0 && (ranges_overlap(op.x_snap, blk_bytes * op.snap_count, Bv, blk_bytes) ||
-                              ranges_overlap(op.x_snap, blk_bytes * op.snap_count, Xv, blk_bytes)))
-        return WD_EINVAL;
-    if ((op.prec_inner == WD_F32 || op.prec_inner == WD_BF16) && op.precond == WD_PRECOND_JACOBI) {
-        int r = lowp_ensure(c);
-        if (r) return r;
-    }
-
+// State of one solve: options, the whole block's column norms, and what the
+// runs of all (sub-)blocks report.
+struct Driver {
     Solver S;
-    S.c = c;
-    S.L = L;
-    S.N = N;
-    S.nb = gram_blocks(N);
-    S.j = op.j;
-    S.precond = op.precond;
-    S.coef = coef_prec(op.prec_inner) ? (int)coef_of(op.prec_inner) : 0;
-    S.pin = S.coef ? Prec::F64 : (Prec)op.prec_inner;
-    S.sl = small_layout(c);
-    S.bufs = SolverBufs{S.sl.C_r, S.sl.C_rn, S.sl.alpha, S.sl.gamma, S.sl.zeta, S.sl.ctl->norms,
-                        &S.sl.ctl->status};
+    wd_solve_opts op{};
+    double tol = 0.0;
+    int max_iter = 0, max_restarts = 0, stag = 0, cycle_stag = 0;
+    static constexpr int max_cycles = 200;
+    double diverge_at = 0.0;
+    double cycle_tol = -1.0;  // > 0: Krylov cycles of an inexact M
+    int fb_j = 0;             // Jacobi steps of the FP64 fallback
+    double bnorm[WD_MAX_L] = {};
+    int iters = 0, total_iters = 0, restarts = 0, cycles = 0, snaps = 0, splits = 0, min_block = WD_MAX_L;
+    bool fell_back = false;
+    double cond_max = 0.0;
+    long long snap_clock = 0;
+    int hist_pos = 0;
+    double true_rel[WD_MAX_L] = {}, rec_rel[WD_MAX_L] = {};
+
+    void record(double res, double gap, double cond) {
+        if (hist_pos < op.history_len) {
+            if (op.history) op.history[hist_pos] = res;
+            if (op.gap_history) op.gap_history[hist_pos] = gap;
+            if (op.cond_history) op.cond_history[hist_pos] = cond;
+        }
+        ++hist_pos;
+    }
+    // largest per-column ||R - (B - A X)|| / ||b|| over the columns [col0, col0 + L) (diagnostic)
+    int gap(const double2* B, const double2* X, const double2* R, int col0, double* out) {
+        Solver& s = S;
+        double2* T1 = s.ws(WS_T1);
+        const size_t n = s.N * s.L;
+        int r = s.applyA(X, T1, false);
+        if (r) return r;
+        WD_TRY_HIP(launch_axpby_block(B, T1, T1, n, s.c->stream));  // B - A X
+        WD_TRY_HIP(launch_axpby_block(R, T1, T1, n, s.c->stream));  // R - (B - A X)
+        s.blocks(6);
+        double g2[WD_MAX_L];
+        if ((r = s.norms(T1, g2))) return r;
+        double m = 0.0;
+        for (int i = 0; i < s.L; ++i) m = std::fmax(m, std::sqrt(g2[i]) / bnorm[col0 + i]);
+        *out = m;
+        return WD_OK;
+    }
+    // FP64 true residual of columns [col0, col0 + L); returns the largest
+    int true_residual(const double2* B, const double2* X, int col0, double* tmax) {
+        Solver& s = S;
+        double2* T1 = s.ws(WS_T1);
+        int r = s.applyA(X, T1, false);
+        if (r) return r;
+        WD_TRY_HIP(launch_axpby_block(B, T1, T1, s.N * s.L, s.c->stream));
+        s.blocks(3);
+        double tr2[WD_MAX_L];
+        if ((r = s.norms(T1, tr2))) return r;
+        *tmax = 0.0;
+        for (int i = 0; i < s.L; ++i) {
+            true_rel[col0 + i] = std::sqrt(tr2[i]) / bnorm[col0 + i];
+            *tmax = std::fmax(*tmax, std::isfinite(true_rel[col0 + i]) ? true_rel[col0 + i] : INFINITY);
+        }
+        return WD_OK;
+    }
+};
+
+constexpr int kCycleEnd = 100;  // internal run status: restart from X
+
+// Solve the columns [col0, col0 + L) of the system; B and X point at the first
+// of them.  Runs the block BiCGGR iteration, its Krylov cycles and FP64
+// fallback for an inexact M, true-residual restarts and, after a failed FP64
+// run, the recursive split of the block into halves.
+int solve_block(Driver& D, const double2* B, double2* X, int col0, int L, bool use_x0) {
+    Solver& S = D.S;
+    wd_ctx* c = S.c;
+    const size_t N = S.N;
     hipStream_t st = c->stream;
-    const double2* B = (const double2*)Bv;
-    double2* X = (double2*)Xv;
+    S.L = L;
+    if (L < D.min_block) D.min_block = L;
+    const double* bnorm = D.bnorm + col0;
+    double* rec_rel = D.rec_rel + col0;
     double2 *R = S.ws(WS_R), *Rt = S.ws(WS_RT), *P = S.ws(WS_P), *V = S.ws(WS_V), *W = S.ws(WS_W),
             *F = S.ws(WS_F), *G = S.ws(WS_G), *U = S.ws(WS_U), *Y = S.ws(WS_Y), *T1 = S.ws(WS_T1);
-
-    WD_TRY_HIP(hipStreamSynchronize(st));
-    const auto t0 = std::chrono::steady_clock::now();
-
-    double bn2[WD_MAX_L];
-    int r = colnorms_host(c, B, L, bn2);
-    if (r) return r;
-    double bnorm[WD_MAX_L];
-    for (int i = 0; i < L; ++i) {
-        if (!std::isfinite(bn2[i])) return WD_ENAN;
-        if (bn2[i] == 0.0) return WD_EINVAL;
-        bnorm[i] = std::sqrt(bn2[i]);
-    }
-
+    double2* Xrec = S.ws(WS_T2);  // recovery point of a run (a cycle's best iterate when cycling)
+    const bool whole = col0 == 0 && L == S.Ltot;
     Ctl* hc = reinterpret_cast<Ctl*>(c->host_ctl);
+    int r = WD_OK;
     int status = WD_NOT_CONVERGED;
-    int iters = 0, total_iters = 0, restarts = 0, cycles = 0, hist_pos = 0;
-    long long snap_clock = 0;  // outer iterations over all runs, for the snapshots
-    int snaps = 0;
-    bool use_x0 = op.use_x0 != 0;
-    double true_rel[WD_MAX_L] = {0}, rec_rel[WD_MAX_L] = {0};
-    // Krylov cycles for an inexact M (low-precision storage of the Jacobi preconditioner)
-    const bool inexact_M = (op.prec_inner == WD_F32 || op.prec_inner == WD_BF16) &&
-                           (op.precond == WD_PRECOND_LEARNED || (op.precond == WD_PRECOND_JACOBI && op.j > 0));
-    double cycle_tol = op.cycle_tol;
-    if (cycle_tol == 0.0) cycle_tol = inexact_M ? (op.prec_inner == WD_F32 ? 1e-4 : 1e-1) : -1.0;
-    bool cycling = cycle_tol > 0.0;
-    bool fell_back = false;
-    const int cycle_stag = op.stagnate_window > 0 ? op.stagnate_window : 20;  // no-improvement limit of a cycle
-    const int max_cycles = 200;
-    double2* Xbest = S.ws(WS_T2);
-    constexpr int kCycleEnd = 100;  // internal run status: restart from X
-
-    auto record = [&](double v) {
-        if (op.history && hist_pos < op.history_len) op.history[hist_pos] = v;
-        ++hist_pos;
-    };
-
     for (;;) {
-        ++cycles;
+        ++D.cycles;
+        const bool cycling = D.cycle_tol > 0.0;
         // ---- initialisation: R0 = B - A X0, P0 = R0, Rt0 = R0, F0 = M R0, V0 = W0 = A F0
         if (use_x0) {
             if ((r = S.applyA(X, T1))) return r;
             WD_TRY_HIP(launch_axpby_block(B, T1, R, N * L, st));
+            S.blocks(3);
         } else {
             WD_TRY_HIP(launch_zero(X, N * L, st));
-            WD_TRY_HIP(launch_copy(R, B, N * L, st));
-            S.mvm_paper += 1;  // R0 = B - A X0 counts as one application (Table 1 convention)
+            S.blocks(1);
+            if ((r = S.copy(R, B))) return r;
+            S.mvm_paper += L;  // R0 = B - A X0 counts as one application (Table 1 convention)
         }
-        WD_TRY_HIP(launch_copy(P, R, N * L, st));
-        WD_TRY_HIP(launch_copy(Rt, R, N * L, st));
+        if ((r = S.copy(P, R))) return r;
+        if ((r = S.copy(Rt, R))) return r;
         if ((r = S.applyM(R, F))) return r;
         if ((r = S.applyA(F, W))) return r;
-        WD_TRY_HIP(launch_copy(V, W, N * L, st));
+        if ((r = S.copy(V, W))) return r;
         if ((r = S.gram_into(Rt, R, S.sl.C_r))) return r;
         WD_TRY_HIP(launch_zero(reinterpret_cast<double2*>(S.sl.ctl), (sizeof(Ctl) + 15) / 16, st));
         double rn2[WD_MAX_L];
-        if ((r = colnorms_host(c, R, L, rn2))) return r;
+        if ((r = S.norms(R, rn2))) return r;
         double res = 0.0;
         for (int i = 0; i < L; ++i) {
             rec_rel[i] = std::sqrt(rn2[i]) / bnorm[i];
             res = std::fmax(res, rec_rel[i]);
         }
-        if (!std::isfinite(res)) {
-            status = WD_ENAN;
-            break;
-        }
-        record(res);
-        iters = 0;
+        if (!std::isfinite(res)) return WD_ENAN;
+        D.record(res, 0.0, 0.0);
+        int iters = 0;
         int run_status = WD_NOT_CONVERGED;
         const double res0 = res;
-        double best = res;
+        double best = res, saved = res;
         int best_k = 0;
-        if (cycling) {  // Xbest: the best iterate of the cycle so far, starting with its initial X
-            WD_TRY_HIP(launch_copy(Xbest, X, N * L, st));
-            S.blocks(2);
+        // the recovery point starts as the run's initial X
+        if (use_x0) {
+            if ((r = S.copy(Xrec, X))) return r;
+        } else {
+            WD_TRY_HIP(launch_zero(Xrec, N * L, st));
+            S.blocks(1);
         }
-        if (res <= tol) run_status = WD_OK;
-        for (int k = 0; run_status == WD_NOT_CONVERGED && k < max_iter; ++k) {
+        if (res <= D.tol) run_status = WD_OK;
+        for (int k = 0; run_status == WD_NOT_CONVERGED && k < D.max_iter; ++k) {
             // alpha and zeta; after the first iteration the P / V update of the previous one
             // has already left Rt^H V, Tr[W^H R] and Tr[W^H W] in the partial blocks
             if (k == 0) {
@@ -608,12 +622,13 @@ int bbicggr_solve(wd_ctx* c, const void* Bv, void* Xv, int L, double tol, const 
             WD_TRY_HIP(launch_solve_alpha(c->partial, S.nb, L, S.bufs, st));
             // U = (P - zeta V) alpha ; G = M U ; Y = A G
             WD_TRY_HIP(launch_update_U(P, V, S.sl.zeta, S.sl.alpha, U, N, L, st));
-            S.blocks(3 + 9);  // U; X, R update with Rt^H R_{k+1} and the norms
+            S.blocks(3);
             const long long mp = S.mvm_paper, ma = S.mvm_actual;
             if ((r = S.applyM(U, G))) return r;
             if ((r = S.applyA(G, Y))) return r;
             // X += zeta F + G ; R -= zeta W + Y ; Rt^H R_{k+1}, norms ; gamma
             WD_TRY_HIP(launch_update_XR_gram(X, R, F, G, W, Y, Rt, S.sl.zeta, N, L, c->partial, S.nb, st));
+            S.blocks(9);
             WD_TRY_HIP(launch_solve_gamma(c->partial, S.nb, L, S.bufs, st));
             if ((r = S.fetch_ctl(hc))) return r;
             if (hc->status & 1) {  // alpha system singular: X and R were left unchanged
@@ -623,10 +638,11 @@ int bbicggr_solve(wd_ctx* c, const void* Bv, void* Xv, int L, double tol, const 
                 break;
             }
             iters = k + 1;
-            ++snap_clock;
-            if (snaps < op.snap_count && snap_clock % op.snap_every == 0) {
-                WD_TRY_HIP(launch_copy((double2*)op.x_snap + (size_t)snaps * N * L, X, N * L, st));
-                ++snaps;
+            ++D.snap_clock;
+            if (whole && D.snaps < D.op.snap_count && D.snap_clock % D.op.snap_every == 0) {
+                WD_TRY_HIP(launch_copy((double2*)D.op.x_snap + (size_t)D.snaps * N * L, X, N * L, st));
+                S.blocks(2);
+                ++D.snaps;
             }
             res = 0.0;
             bool nan = (hc->status & 4) != 0;
@@ -635,47 +651,53 @@ int bbicggr_solve(wd_ctx* c, const void* Bv, void* Xv, int L, double tol, const 
                 if (!std::isfinite(rec_rel[i])) nan = true;
                 res = std::fmax(res, rec_rel[i]);
             }
-            record(res);
+            const double cond = std::fmax(hc->cond[0], hc->cond[1]);
+            D.cond_max = std::fmax(D.cond_max, cond);
+            double gapv = 0.0;
+            if (D.op.gap_history && (r = D.gap(B, X, R, col0, &gapv))) return r;
+            D.record(res, gapv, cond);
             if (nan) {
                 run_status = WD_ENAN;
                 break;
             }
-            if (res <= tol) {
+            if (res <= D.tol) {
                 run_status = WD_OK;
                 break;
             }
-            if (cycling && res <= cycle_tol * res0) {
+            if (cycling && res <= D.cycle_tol * res0) {
                 run_status = kCycleEnd;
                 break;
             }
-            const int window = cycling ? cycle_stag : stag;
-            if (res > diverge_at) {
+            if (res > D.diverge_at) {
                 run_status = WD_DIVERGED;
                 break;
             }
             if (res < best) {
                 best = res;
                 best_k = k + 1;
-                if (cycling) {
-                    WD_TRY_HIP(launch_copy(Xbest, X, N * L, st));
-                    S.blocks(2);
-                }
-            } else if (k + 1 - best_k >= window) {
+                if (cycling && (r = S.copy(Xrec, X))) return r;
+            } else if (k + 1 - best_k >= (cycling ? D.cycle_stag : D.stag)) {
                 run_status = WD_STAGNATED;
+                break;
+            }
+            if (!cycling && res < 0.1 * saved) {
+                if ((r = S.copy(Xrec, X))) return r;
+                saved = res;
+            }
+            // rank loss of the block: a singular gamma system, or a condition estimate past the limit
+            if ((hc->status & 2) || (D.op.cond_limit > 0.0 && !(cond <= D.op.cond_limit))) {
+                run_status = WD_BREAKDOWN;
                 break;
             }
             // F = M R_{k+1} ; W = A F
             if ((r = S.applyM(R, F))) return r;
             if ((r = S.applyA(F, W))) return r;
-            if (hc->status & 2) {
-                run_status = WD_BREAKDOWN;
-                break;
-            }
             // P = R + U gamma ; V = W + Y gamma, with the next iteration's Gram products
             WD_TRY_HIP(launch_update_PV_gram(P, V, R, W, U, Y, S.sl.gamma, Rt, N, L, c->partial, S.nb, st));
             S.blocks(7);
         }
-        total_iters += iters;
+        D.iters = iters;
+        D.total_iters += iters;
         // an inexact M whose cycle stalled, blew up or broke down.  Unless the caller turned the
         // fallback off, the solve starts again from X0 = 0 (so R~0 = R0 = B, as in a plain solve)
         // with the FP64 Jacobi preconditioner: restarted from the inexact iterate, FP64 block
@@ -683,40 +705,57 @@ int bbicggr_solve(wd_ctx* c, const void* Bv, void* Xv, int L, double tol, const 
         // fallback X returns to the cycle's best iterate.
         if (cycling && (run_status == WD_STAGNATED || run_status == WD_DIVERGED || run_status == WD_BREAKDOWN ||
                         run_status == WD_NOT_CONVERGED)) {
-            if (!op.no_fallback && run_status != WD_NOT_CONVERGED) {
-                S.precond = fb_j > 0 ? WD_PRECOND_JACOBI : WD_PRECOND_NONE;
-                S.j = fb_j;
+            if (!D.op.no_fallback && run_status != WD_NOT_CONVERGED) {
+                S.precond = D.fb_j > 0 ? WD_PRECOND_JACOBI : WD_PRECOND_NONE;
+                S.j = D.fb_j;
                 S.pin = Prec::F64;
                 S.coef = 0;
-                cycling = false;
-                fell_back = true;
+                D.cycle_tol = -1.0;
+                D.fell_back = true;
                 use_x0 = false;
                 continue;
             }
-            WD_TRY_HIP(launch_copy(X, Xbest, N * L, st));
-            S.blocks(2);
+            if ((r = S.copy(X, Xrec))) return r;
         }
-        if (run_status == kCycleEnd && cycles < max_cycles) {
+        if (run_status == kCycleEnd && D.cycles < D.max_cycles) {
             use_x0 = true;
             continue;
         }
         if (run_status == kCycleEnd) run_status = WD_NOT_CONVERGED;
         status = run_status;
-        if (status == WD_ENAN) break;
-        // ---- true residual ||B - A X|| / ||B|| in FP64
-        WD_TRY_HIP(launch_apply_A(c, X, T1, L, st));
-        S.mvm_actual += 1;
-        WD_TRY_HIP(launch_axpby_block(B, T1, T1, N * L, st));
-        double tr2[WD_MAX_L];
-        if ((r = colnorms_host(c, T1, L, tr2))) return r;
-        double tmax = 0.0;
-        for (int i = 0; i < L; ++i) {
-            true_rel[i] = std::sqrt(tr2[i]) / bnorm[i];
-            tmax = std::fmax(tmax, std::isfinite(true_rel[i]) ? true_rel[i] : INFINITY);
+        if (status == WD_ENAN) return WD_ENAN;
+        if (!cycling && status != WD_OK) {
+            // a diverged or stagnated FP64 run goes back to its recovery point unless the last
+            // iterate is at least as good (a breakdown stops on a sound iterate; at max_iter the
+            // last iterate is returned)
+            if ((status == WD_DIVERGED || status == WD_STAGNATED) && res > saved && (r = S.copy(X, Xrec)))
+                return r;
+            if (status != WD_NOT_CONVERGED) {
+                if (L > 1 && !D.op.no_split) {
+                    // Sec. 3.3: repeat the inversion with smaller L -- each half of the block
+                    // is solved on its own from the current X (recursively)
+                    ++D.splits;
+                    const int La = (L + 1) / 2;
+                    const int ra = solve_block(D, B, X, col0, La, true);
+                    if (ra < 0) return ra;
+                    const int rb = solve_block(D, B + (size_t)La * N, X + (size_t)La * N, col0 + La, L - La, true);
+                    if (rb < 0) return rb;
+                    S.L = L;
+                    return ra != WD_OK ? ra : rb;
+                }
+                if (D.restarts < D.max_restarts) {
+                    ++D.restarts;
+                    use_x0 = true;
+                    continue;
+                }
+            }
         }
-        if (status == WD_OK && tmax > tol) {
-            if (restarts < max_restarts) {
-                ++restarts;
+        // ---- true residual ||B - A X|| / ||B|| in FP64
+        double tmax = 0.0;
+        if ((r = D.true_residual(B, X, col0, &tmax))) return r;
+        if (status == WD_OK && tmax > D.tol) {
+            if (D.restarts < D.max_restarts) {
+                ++D.restarts;
                 use_x0 = true;
                 continue;
             }
@@ -724,27 +763,284 @@ int bbicggr_solve(wd_ctx* c, const void* Bv, void* Xv, int L, double tol, const 
         }
         break;
     }
-    WD_TRY_HIP(hipStreamSynchronize(st));
-    const double secs = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
-    if (info) {
-        std::memset(info, 0, sizeof(*info));
-        info->status = status < 0 ? WD_NOT_CONVERGED : status;
-        info->iterations = iters;
-        info->total_iterations = total_iters;
-        info->restarts = restarts;
-        info->cycles = cycles;
-        info->fallback = fell_back ? 1 : 0;
-        info->snapshots = snaps;
-        info->mvm_paper = S.mvm_paper;
-        info->mvm_actual = S.mvm_actual;
-        info->seconds = secs;
-        info->bytes_alg = S.bytes;
-        for (int i = 0; i < L; ++i) {
-            info->true_residual[i] = true_rel[i];
-            info->recursive_residual[i] = rec_rel[i];
+    return status;
+}
+
+// Block BiCGSTAB on the whole block (the foil): same initialisation, stopping
+// rule, recovery point and true-residual restarts as above.
+int stab_solve(Driver& D, const double2* B, double2* X, bool use_x0) {
+    Solver& S = D.S;
+    wd_ctx* c = S.c;
+    const size_t N = S.N;
+    const int L = S.L;
+    hipStream_t st = c->stream;
+    D.min_block = L;
+    const SmallLayout& sl = S.sl;
+    double2 *R = S.ws(WS_R), *Rt = S.ws(WS_RT), *P = S.ws(WS_P), *V = S.ws(WS_V), *Ph = S.ws(WS_F),
+            *Sb = S.ws(WS_U), *Sh = S.ws(WS_G), *T = S.ws(WS_Y), *T1 = S.ws(WS_T1);
+    double2* Xrec = S.ws(WS_T2);
+    // L x L matrices: Rt^H R, Rt^H V, alpha, beta, Rt^H T, T^H S, T^H T; omega in the scalars
+    double2 *C_r = sl.mats[0], *C_v = sl.mats[1], *alpha = sl.mats[2], *beta = sl.mats[3], *C_t = sl.mats[4],
+            *C_ts = sl.mats[5], *C_tt = sl.mats[6], *omega = sl.zeta + 4;
+    const double2 one = make_double2(1.0, 0.0), mone = make_double2(-1.0, 0.0), zero = make_double2(0.0, 0.0);
+    int* flags = &sl.ctl->status;
+    Ctl* hc = reinterpret_cast<Ctl*>(c->host_ctl);
+    int r = WD_OK;
+    int status = WD_NOT_CONVERGED;
+    for (;;) {
+        ++D.cycles;
+        if (use_x0) {
+            if ((r = S.applyA(X, T1))) return r;
+            WD_TRY_HIP(launch_axpby_block(B, T1, R, N * L, st));
+            S.blocks(3);
+        } else {
+            WD_TRY_HIP(launch_zero(X, N * L, st));
+            S.blocks(1);
+            if ((r = S.copy(R, B))) return r;
+            S.mvm_paper += L;
         }
+        if ((r = S.copy(P, R))) return r;
+        if ((r = S.copy(Rt, R))) return r;
+        if ((r = S.gram_into(Rt, R, C_r))) return r;
+        WD_TRY_HIP(launch_zero(reinterpret_cast<double2*>(sl.ctl), (sizeof(Ctl) + 15) / 16, st));
+        double rn2[WD_MAX_L];
+        if ((r = S.norms(R, rn2))) return r;
+        double res = 0.0;
+        for (int i = 0; i < L; ++i) {
+            D.rec_rel[i] = std::sqrt(rn2[i]) / D.bnorm[i];
+            res = std::fmax(res, D.rec_rel[i]);
+        }
+        if (!std::isfinite(res)) return WD_ENAN;
+        D.record(res, 0.0, 0.0);
+        int iters = 0, run_status = WD_NOT_CONVERGED;
+        double best = res, saved = res;
+        int best_k = 0;
+        if (use_x0) {
+            if ((r = S.copy(Xrec, X))) return r;
+        } else {
+            WD_TRY_HIP(launch_zero(Xrec, N * L, st));
+            S.blocks(1);
+        }
+        if (res <= D.tol) run_status = WD_OK;
+        for (int k = 0; run_status == WD_NOT_CONVERGED && k < D.max_iter; ++k) {
+            if ((r = S.applyM(P, Ph))) return r;                     // Ph = M P
+            if ((r = S.applyA(Ph, V))) return r;                     // V = A Ph
+            if ((r = S.gram_into(Rt, V, C_v))) return r;             // Rt^H V
+            WD_TRY_HIP(launch_small_solve_scaled(C_v, C_r, L, one, alpha, flags, 1, &sl.ctl->cond[0], st));
+            WD_TRY_HIP(launch_block_comb(Sb, R, nullptr, V, nullptr, alpha, one, zero, mone, zero, nullptr, 0, N, L,
+                                         st));                       // S = R - V alpha
+            S.blocks(3);
+            if ((r = S.applyM(Sb, Sh))) return r;                    // Sh = M S
+            if ((r = S.applyA(Sh, T))) return r;                     // T = A Sh
+            if ((r = S.gram_into(T, Sb, C_ts))) return r;
+            if ((r = S.gram_into(T, T, C_tt))) return r;
+            WD_TRY_HIP(launch_stab_omega(C_ts, C_tt, L, omega, flags, 2, st));
+            // X += Ph alpha + omega Sh ; R = S - omega T
+            WD_TRY_HIP(launch_block_comb(X, X, Sh, Ph, nullptr, alpha, one, one, one, zero, omega, 2, N, L, st));
+            WD_TRY_HIP(launch_block_comb(R, Sb, T, nullptr, nullptr, nullptr, one, mone, zero, zero, omega, 2, N, L,
+                                         st));
+            S.blocks(4 + 3);
+            WD_TRY_HIP(launch_colnorms(R, N, L, c->partial, S.nb, sl.ctl->norms, st));
+            S.blocks(1);
+            if ((r = S.fetch_ctl(hc))) return r;
+            iters = k + 1;
+            res = 0.0;
+            bool nan = false;
+            for (int i = 0; i < L; ++i) {
+                D.rec_rel[i] = std::sqrt(hc->norms[i]) / D.bnorm[i];
+                if (!std::isfinite(D.rec_rel[i])) nan = true;
+                res = std::fmax(res, D.rec_rel[i]);
+            }
+            const double cond = hc->cond[0];
+            D.cond_max = std::fmax(D.cond_max, cond);
+            double gapv = 0.0;
+            if (D.op.gap_history && (r = D.gap(B, X, R, 0, &gapv))) return r;
+            D.record(res, gapv, cond);
+            if (nan) {
+                run_status = WD_ENAN;
+                break;
+            }
+            if (hc->status & 3) {  // singular Rt^H V or zero Tr[T^H T]
+                run_status = WD_BREAKDOWN;
+                break;
+            }
+            if (res <= D.tol) {
+                run_status = WD_OK;
+                break;
+            }
+            if (res > D.diverge_at) {
+                run_status = WD_DIVERGED;
+                break;
+            }
+            if (res < best) {
+                best = res;
+                best_k = k + 1;
+            } else if (k + 1 - best_k >= D.stag) {
+                run_status = WD_STAGNATED;
+                break;
+            }
+            if (res < 0.1 * saved) {
+                if ((r = S.copy(Xrec, X))) return r;
+                saved = res;
+            }
+            if (D.op.cond_limit > 0.0 && !(cond <= D.op.cond_limit)) {
+                run_status = WD_BREAKDOWN;
+                break;
+            }
+            // beta: (Rt^H V) beta = -Rt^H T ; P = R + (P - omega V) beta ; Rt^H R_{k+1}
+            if ((r = S.gram_into(Rt, T, C_t))) return r;
+            WD_TRY_HIP(launch_small_solve_scaled(C_v, C_t, L, mone, beta, flags, 1, nullptr, st));
+            WD_TRY_HIP(launch_block_comb(P, R, nullptr, P, V, beta, one, zero, one, mone, omega, 8, N, L, st));
+            S.blocks(4);
+            if ((r = S.gram_into(Rt, R, C_r))) return r;
+        }
+        D.iters = iters;
+        D.total_iters += iters;
+        status = run_status;
+        if (status == WD_ENAN) return WD_ENAN;
+        if (status != WD_OK) {
+            if ((status == WD_DIVERGED || status == WD_STAGNATED) && res > saved && (r = S.copy(X, Xrec)))
+                return r;
+            if (status != WD_NOT_CONVERGED && D.restarts < D.max_restarts) {
+                ++D.restarts;
+                use_x0 = true;
+                continue;
+            }
+        }
+        double tmax = 0.0;
+        if ((r = D.true_residual(B, X, 0, &tmax))) return r;
+        if (status == WD_OK && tmax > D.tol) {
+            if (D.restarts < D.max_restarts) {
+                ++D.restarts;
+                use_x0 = true;
+                continue;
+            }
+            status = WD_NOT_CONVERGED;
+        }
+        break;
     }
     return status;
+}
+
+void fill_info(const Driver& D, int rc, double secs, int L, wd_solve_info* info) {
+    if (!info) return;
+    std::memset(info, 0, sizeof(*info));
+    info->status = rc;
+    info->iterations = D.iters;
+    info->total_iterations = D.total_iters;
+    info->restarts = D.restarts;
+    info->cycles = D.cycles;
+    info->fallback = D.fell_back ? 1 : 0;
+    info->snapshots = D.snaps;
+    info->mvm_paper = D.S.mvm_paper / L;
+    info->mvm_actual = D.S.mvm_actual / L;
+    info->seconds = secs;
+    info->bytes_alg = D.S.bytes;
+    for (int i = 0; i < L; ++i) {
+        info->true_residual[i] = D.true_rel[i];
+        info->recursive_residual[i] = D.rec_rel[i];
+    }
+    info->cond_max = D.cond_max;
+    info->splits = D.splits;
+    info->min_block = D.min_block;
+}
+
+// Argument checks and set-up shared by both solvers; returns 0 or an error.
+int solve_setup(wd_ctx* c, const void* Bv, void* Xv, int L, double tol, const wd_solve_opts* o, bool stab,
+                Driver& D) {
+    if (!c || !Bv || !Xv) return WD_EINVAL;
+    if (L < 1 || L > c->max_L || !(tol > 0.0)) return WD_EINVAL;
+    if (!c->have_params) return WD_ESTATE;
+    wd_solve_opts& op = D.op;
+    if (o) op = *o;
+    if (op.precond != WD_PRECOND_NONE && op.precond != WD_PRECOND_JACOBI && op.precond != WD_PRECOND_LEARNED)
+        return WD_EINVAL;
+    if (op.j < 0 || (check_prec(op.prec_inner) && !coef_prec(op.prec_inner))) return WD_EINVAL;
+    if (op.snap_count < 0 || (op.snap_count > 0 && (!op.x_snap || op.snap_every < 1))) return WD_EINVAL;
+    if (op.history_len < 0) return WD_EINVAL;
+    if (stab && (op.precond == WD_PRECOND_LEARNED || op.prec_inner != WD_F64 || op.snap_count > 0))
+        return WD_EINVAL;
+    if (op.precond == WD_PRECOND_LEARNED) {
+        if (op.prec_inner == WD_BF16 || coef_prec(op.prec_inner)) return WD_EINVAL;
+        if (!c->have_theta) return WD_ESTATE;
+        int r0 = learned_ensure(c);
+        if (r0) return r0;
+    }
+    const size_t N = (size_t)12 * c->g.V;
+    const size_t blk_bytes = N * L * 16;
+    if (overlap(Bv, Xv, blk_bytes)) return WD_EINVAL;
+    if (op.snap_count > 0 && (ranges_overlap(op.x_snap, blk_bytes * op.snap_count, Bv, blk_bytes) ||
+                              ranges_overlap(op.x_snap, blk_bytes * op.snap_count, Xv, blk_bytes)))
+        return WD_EINVAL;
+    if ((op.prec_inner == WD_F32 || op.prec_inner == WD_BF16) && op.precond == WD_PRECOND_JACOBI) {
+        int r = lowp_ensure(c);
+        if (r) return r;
+    }
+    // FP64 fallback for an inexact M whose cycles stall: Jacobi in FP64 with the caller's j (M = I if 0)
+    D.fb_j = op.j;
+    if (op.precond != WD_PRECOND_JACOBI) op.j = 0;
+    D.tol = tol;
+    D.max_iter = op.max_iter > 0 ? op.max_iter : 5000;
+    D.max_restarts = op.max_restarts >= 0 ? op.max_restarts : 3;
+    D.stag = op.stagnate_window > 0 ? op.stagnate_window : 200;
+    D.cycle_stag = op.stagnate_window > 0 ? op.stagnate_window : 20;  // no-improvement limit of a cycle
+    D.diverge_at = op.diverge_at > 0 ? op.diverge_at : 1e2;
+    // Krylov cycles for an inexact M (low-precision storage of the Jacobi preconditioner)
+    const bool inexact_M = (op.prec_inner == WD_F32 || op.prec_inner == WD_BF16) &&
+                           (op.precond == WD_PRECOND_LEARNED || (op.precond == WD_PRECOND_JACOBI && op.j > 0));
+    D.cycle_tol = op.cycle_tol;
+    if (D.cycle_tol == 0.0) D.cycle_tol = inexact_M ? (op.prec_inner == WD_F32 ? 1e-4 : 1e-1) : -1.0;
+    Solver& S = D.S;
+    S.c = c;
+    S.L = L;
+    S.Ltot = L;
+    S.N = N;
+    S.nb = gram_blocks(N);
+    S.j = op.j;
+    S.precond = op.precond;
+    S.coef = coef_prec(op.prec_inner) ? (int)coef_of(op.prec_inner) : 0;
+    S.pin = S.coef ? Prec::F64 : (Prec)op.prec_inner;
+    S.sl = small_layout(c);
+    S.bufs = SolverBufs{S.sl.C_r,       S.sl.C_rn,         S.sl.alpha,          S.sl.gamma,
+                        S.sl.zeta,      S.sl.ctl->norms,   &S.sl.ctl->status,   S.sl.ctl->cond};
+    return WD_OK;
+}
+
+int solve_common(wd_ctx* c, const void* Bv, void* Xv, int L, double tol, const wd_solve_opts* o,
+                 wd_solve_info* info, bool stab) {
+    Driver D;
+    int rc = solve_setup(c, Bv, Xv, L, tol, o, stab, D);
+    if (rc) return rc;  // argument errors: nothing modified
+    const auto t0 = std::chrono::steady_clock::now();
+    const double2* B = (const double2*)Bv;
+    double2* X = (double2*)Xv;
+    rc = hipStreamSynchronize(c->stream) == hipSuccess ? WD_OK : WD_EHIP;
+    if (rc == WD_OK) {
+        double bn2[WD_MAX_L];
+        rc = D.S.norms(B, bn2);
+        for (int i = 0; i < L && rc == WD_OK; ++i) {
+            if (!std::isfinite(bn2[i])) rc = WD_ENAN;
+            else if (bn2[i] == 0.0) rc = WD_EINVAL;
+            else D.bnorm[i] = std::sqrt(bn2[i]);
+        }
+    }
+    if (rc == WD_OK) rc = stab ? stab_solve(D, B, X, D.op.use_x0 != 0) : solve_block(D, B, X, 0, L, D.op.use_x0 != 0);
+    if (hipStreamSynchronize(c->stream) != hipSuccess && rc >= 0) rc = WD_EHIP;
+    const double secs = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+    fill_info(D, rc, secs, L, info);
+    return rc;
+}
+
+}  // namespace
+
+int bbicggr_solve(wd_ctx* c, const void* Bv, void* Xv, int L, double tol, const wd_solve_opts* o,
+                  wd_solve_info* info) {
+    return solve_common(c, Bv, Xv, L, tol, o, info, false);
+}
+
+int bbicgstab_solve(wd_ctx* c, const void* Bv, void* Xv, int L, double tol, const wd_solve_opts* o,
+                    wd_solve_info* info) {
+    return solve_common(c, Bv, Xv, L, tol, o, info, true);
 }
 
 }  // extern "C"

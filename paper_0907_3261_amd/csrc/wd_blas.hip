@@ -243,17 +243,24 @@ struct SolveShared {
     double2 aug[16 * 32];
     double fac[2 * 16];
     double scale;
+    double pmin, pmax;  // smallest and largest pivot modulus of the last factorisation
     int piv;
     int flag;
 };
 
 // Solve M Z = RHS (L x L row-major in shared memory) by LU with partial
 // pivoting into sm.sol (row-major).  Returns false (uniformly across the
-// workgroup) on a pivot below 1e-14 max|M| or a non-finite entry.
+// workgroup) on a pivot below 1e-14 max|M| or a non-finite entry.  The
+// ratio sm.pmax / sm.pmin of the pivot moduli is a cheap estimate of the
+// condition of M (a lower bound of it for this pivot order).
 __device__ bool lu_solve_shared(SolveShared& sm, int L) {
     const int t = threadIdx.x;
     const int W2 = 2 * L;
-    if (t == 0) sm.flag = 0;
+    if (t == 0) {
+        sm.flag = 0;
+        sm.pmin = INFINITY;
+        sm.pmax = 0.0;
+    }
     __syncthreads();
     if (t < L * W2) {
         const int r = t / W2, c = t % W2;
@@ -288,7 +295,10 @@ __device__ bool lu_solve_shared(SolveShared& sm, int L) {
                     p = r;
                 }
             }
-            if (!(sqrt(best) >= thr)) sm.flag = 1;
+            const double pm = sqrt(best);
+            if (!(pm >= thr)) sm.flag = 1;
+            sm.pmin = fmin(sm.pmin, pm);
+            sm.pmax = fmax(sm.pmax, pm);
             sm.piv = p;
         }
         __syncthreads();
@@ -354,18 +364,32 @@ __global__ void __launch_bounds__(kRT) k_reduce_extras(const double2* __restrict
     if ((int)threadIdx.x < n) out[threadIdx.x] = sm.red[threadIdx.x].x;
 }
 
+__device__ __forceinline__ double cond_of(const SolveShared& sm, bool ok) {
+    return ok ? sm.pmax / sm.pmin : INFINITY;
+}
+
+// Z = M^{-1} (c RHS) for a complex scale c, by LU in LDS; on failure Z = 0.
+// status_bit 0: *status = ok ? 0 : 1; otherwise *status |= status_bit on
+// failure.  cond (may be null) receives the pivot-ratio condition estimate.
 __global__ void __launch_bounds__(kRT) k_small_solve(const double2* __restrict__ M, const double2* __restrict__ RHS,
-                                                     int L, double2* __restrict__ Z, int* __restrict__ status) {
+                                                     int L, double2 c, double2* __restrict__ Z,
+                                                     int* __restrict__ status, int status_bit,
+                                                     double* __restrict__ cond) {
     __shared__ SolveShared sm;
     const int t = threadIdx.x;
     if (t < L * L) {
         sm.M[t] = M[t];
-        sm.RHS[t] = RHS[t];
+        const double2 r = RHS[t];
+        sm.RHS[t] = make_double2(c.x * r.x - c.y * r.y, c.x * r.y + c.y * r.x);
     }
     __syncthreads();
     const bool ok = lu_solve_shared(sm, L);
     if (t < L * L) Z[t] = ok ? sm.sol[t] : make_double2(0.0, 0.0);
-    if (t == 0) status[0] = ok ? 0 : 1;
+    if (t == 0) {
+        if (status_bit == 0) status[0] = ok ? 0 : 1;
+        else if (!ok) status[0] |= status_bit;
+        if (cond) cond[0] = cond_of(sm, ok);
+    }
 }
 
 // Status bits of the solver flags
@@ -389,6 +413,7 @@ __global__ void __launch_bounds__(kRT) k_solve_alpha(const double2* __restrict__
     ok = ok && finite2(twr) && isfinite(tww.x) && tww.x > 0.0;
     if (t < L * L) b.alpha[t] = ok ? sm.sol[t] : make_double2(0.0, 0.0);
     if (t == 0) {
+        b.cond[0] = cond_of(sm, ok);
         b.zeta[0] = ok ? make_double2(twr.x / tww.x, twr.y / tww.x) : make_double2(0.0, 0.0);
         b.zeta[1] = twr;
         b.zeta[2] = tww;
@@ -424,7 +449,10 @@ __global__ void __launch_bounds__(kRT) k_solve_gamma(const double2* __restrict__
         b.C_r[t] = sm.red[t];
         b.C_rn[t] = sm.red[t];
     }
-    if (t == 0 && !ok) b.status[0] |= kGammaBreak;
+    if (t == 0) {
+        b.cond[1] = cond_of(sm, ok);
+        if (!ok) b.status[0] |= kGammaBreak;
+    }
 }
 
 // ---------------------------------------------------------------------------
@@ -626,6 +654,66 @@ __global__ void k_fill0(double2* __restrict__ d, size_t n) {
     if (i < n) d[i] = make_double2(0.0, 0.0);
 }
 
+// ---------------------------------------------------------------------------
+// Block BiCGSTAB helpers (the foil of block BiCGGR)
+// ---------------------------------------------------------------------------
+// out[:, j] = a A[:, j] + b B[:, j] + sum_i (c C[:, i] + d D[:, i]) M[i, j],
+// one thread per row.  Null blocks are left out; the scalars a, b, c, d are
+// multiplied by the device scalar *w where bits 1, 2, 4, 8 of wmask say so.
+// A row's C and D entries are all read before any of its outputs is written
+// and out[:, j] reads only A[:, j] and B[:, j] before it is written, so out
+// may be the same block as A, C or D.
+template <int L>
+__global__ void __launch_bounds__(kWG) k_block_comb(double2* out, const double2* A, const double2* Bm,
+                                                    const double2* C, const double2* D,
+                                                    const double2* __restrict__ M, double2 a, double2 b, double2 c,
+                                                    double2 d, const double2* __restrict__ w, int wmask, size_t N) {
+    const size_t n = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (n >= N) return;
+    cx<double> sa = {a.x, a.y}, sb = {b.x, b.y}, sc = {c.x, c.y}, sd = {d.x, d.y};
+    if (w) {
+        const cx<double> wv = StF64::ld(w, 0);
+        if (wmask & 1) sa = sa * wv;
+        if (wmask & 2) sb = sb * wv;
+        if (wmask & 4) sc = sc * wv;
+        if (wmask & 8) sd = sd * wv;
+    }
+    cx<double> s[L];
+    const bool mix = (C != nullptr || D != nullptr) && M != nullptr;
+#pragma unroll
+    for (int i = 0; i < L; ++i) {
+        s[i] = {0.0, 0.0};
+        if (mix && C) cfma(s[i], sc, StF64::ld(C, (size_t)i * N + n));
+        if (mix && D) cfma(s[i], sd, StF64::ld(D, (size_t)i * N + n));
+    }
+#pragma unroll
+    for (int j = 0; j < L; ++j) {
+        cx<double> v = {0.0, 0.0};
+        if (A) cfma(v, sa, StF64::ld(A, (size_t)j * N + n));
+        if (Bm) cfma(v, sb, StF64::ld(Bm, (size_t)j * N + n));
+        if (mix)
+#pragma unroll
+            for (int i = 0; i < L; ++i) cfma(v, s[i], StF64::ld(M, i * L + j));
+        StF64::st(out, (size_t)j * N + n, v);
+    }
+}
+
+// omega = Tr[T^H S] / Tr[T^H T] from the two L x L Gram matrices; on a zero or
+// non-finite denominator omega = 0 and bit is set in *status.
+__global__ void k_stab_omega(const double2* __restrict__ Cts, const double2* __restrict__ Ctt, int L,
+                             double2* __restrict__ omega, int* __restrict__ status, int bit) {
+    if (threadIdx.x != 0) return;
+    double nr = 0.0, ni = 0.0, dd = 0.0;
+    for (int i = 0; i < L; ++i) {
+        nr += Cts[i * L + i].x;
+        ni += Cts[i * L + i].y;
+        dd += Ctt[i * L + i].x;
+    }
+    const bool ok = isfinite(nr) && isfinite(ni) && isfinite(dd) && dd > 0.0;
+    omega[0] = ok ? make_double2(nr / dd, ni / dd) : make_double2(0.0, 0.0);
+    if (!ok) status[0] |= bit;
+}
+
 inline unsigned nblk(size_t n, unsigned b) { return (unsigned)((n + b - 1) / b); }
 
 }  // namespace
@@ -651,7 +739,13 @@ hipError_t launch_reduce_gram(const double2* partial, int nb, int L, double2* C,
 }
 
 hipError_t launch_small_solve(const double2* M, const double2* RHS, int L, double2* Z, int* status, hipStream_t s) {
-    k_small_solve<<<1, kRT, 0, s>>>(M, RHS, L, Z, status);
+    k_small_solve<<<1, kRT, 0, s>>>(M, RHS, L, make_double2(1.0, 0.0), Z, status, 0, nullptr);
+    return hipGetLastError();
+}
+
+hipError_t launch_small_solve_scaled(const double2* M, const double2* RHS, int L, double2 c, double2* Z, int* status,
+                                     int status_bit, double* cond, hipStream_t s) {
+    k_small_solve<<<1, kRT, 0, s>>>(M, RHS, L, c, Z, status, status_bit, cond);
     return hipGetLastError();
 }
 
@@ -715,6 +809,21 @@ hipError_t launch_update_XR_gram(double2* X, double2* R, const double2* F, const
 #define WD_CALL_XRG(l) k_update_XR_gram<l><<<nb, kWG, 0, s>>>(X, R, F, G, W, Y, zeta, Rt, N, partial, nb)
     WD_L_SWITCH(L, WD_CALL_XRG)
 #undef WD_CALL_XRG
+    return hipGetLastError();
+}
+
+hipError_t launch_block_comb(double2* out, const double2* A, const double2* Bm, const double2* C, const double2* D,
+                             const double2* M, double2 a, double2 b, double2 c, double2 d, const double2* w, int wmask,
+                             size_t N, int L, hipStream_t s) {
+#define WD_CALL_COMB(l) k_block_comb<l><<<nblk(N, kWG), kWG, 0, s>>>(out, A, Bm, C, D, M, a, b, c, d, w, wmask, N)
+    WD_L_SWITCH(L, WD_CALL_COMB)
+#undef WD_CALL_COMB
+    return hipGetLastError();
+}
+
+hipError_t launch_stab_omega(const double2* Cts, const double2* Ctt, int L, double2* omega, int* status, int bit,
+                             hipStream_t s) {
+    k_stab_omega<<<1, 64, 0, s>>>(Cts, Ctt, L, omega, status, bit);
     return hipGetLastError();
 }
 

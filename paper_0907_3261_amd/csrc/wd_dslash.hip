@@ -20,8 +20,6 @@
 //   JBLOCK Y = T^{-1} (Rh + kappa H X)             (Jacobi sweep, A_D = T)
 //   JPOINT Y = D^{-1} (Rh + kappa H X - (T - D) X) (Jacobi sweep, A_D = diag T)
 // The links arrive pre-multiplied by kappa.
-#include <cstdlib>
-
 #include "wd_internal.h"
 
 namespace wd {
@@ -354,27 +352,15 @@ __global__ void k_from_lowp(const typename S::P* __restrict__ src, double2* __re
     dst[i] = make_double2((double)v.re, (double)v.im);
 }
 
-// Streaming-load policy of the hop kernel: default 2 (time-direction
-// neighbours streamed; measured about 5 % faster at 32^3 x 64, L = 12);
-// WDSOLVE_HOP_NT = 0..3 overrides it for three-column tiles (tuning only).
-int hop_ntp() {
-    static int v = [] {
-        const char* e = std::getenv("WDSOLVE_HOP_NT");
-        const int x = e ? std::atoi(e) : 2;
-        return (x >= 0 && x <= 3) ? x : 2;
-    }();
-    return v;
-}
+// Streaming-load policy of the hop kernel: the time-direction neighbours are
+// streamed (measured about 5 % faster at 32^3 x 64, L = 12 than no streaming,
+// streaming the clover as well, or both).
+constexpr int kHopNTP = 2;
 
-// Columns per thread for L right-hand sides (overridable for tuning).
-// FP32 / BF16 storage takes four-column tiles from L = 10 on (measured a few
-// per cent faster than three at L = 12; FP64 is fastest with three).
+// Columns per thread for L right-hand sides.  FP32 / BF16 storage takes
+// four-column tiles from L = 10 on (measured a few per cent faster than three
+// at L = 12; FP64 is fastest with three).
 int tile_cols(int L, bool lowp) {
-    static int forced = [] {
-        const char* e = std::getenv("WDSOLVE_HOP_CT");
-        return e ? std::atoi(e) : 0;
-    }();
-    if (forced >= 1 && forced <= 4) return forced < L ? forced : L;
     if (L <= 2) return 1;
     if (L <= 8) return 2;
     if (L <= 12) return (lowp && L >= 10) ? 4 : 3;
@@ -391,25 +377,8 @@ hipError_t launch_hop_ct(const Geom& g, const void* Uk, const void* Cl, const vo
     using PF = typename SF::P;
     using PY = typename SY::P;
     using PC = typename SC::P;
-    const int ntp = hop_ntp();
-    if constexpr (CT == 3) {
-        if (ntp == 0)
-            k_hop<SF, SY, CT, MODE, 0, SC><<<grid, block, 0, s>>>(g, sm, (const PC*)Uk, (const PC*)Cl, (const PF*)X,
-                                                              (const PF*)Rh, (PY*)Y, col_begin, ntiles);
-        else if (ntp == 1)
-            k_hop<SF, SY, CT, MODE, 1, SC><<<grid, block, 0, s>>>(g, sm, (const PC*)Uk, (const PC*)Cl, (const PF*)X,
-                                                              (const PF*)Rh, (PY*)Y, col_begin, ntiles);
-        else if (ntp == 3)
-            k_hop<SF, SY, CT, MODE, 3, SC><<<grid, block, 0, s>>>(g, sm, (const PC*)Uk, (const PC*)Cl, (const PF*)X,
-                                                              (const PF*)Rh, (PY*)Y, col_begin, ntiles);
-        else
-            k_hop<SF, SY, CT, MODE, 2, SC><<<grid, block, 0, s>>>(g, sm, (const PC*)Uk, (const PC*)Cl, (const PF*)X,
-                                                              (const PF*)Rh, (PY*)Y, col_begin, ntiles);
-    } else {
-        (void)ntp;
-        k_hop<SF, SY, CT, MODE, 2, SC><<<grid, block, 0, s>>>(g, sm, (const PC*)Uk, (const PC*)Cl, (const PF*)X,
-                                                          (const PF*)Rh, (PY*)Y, col_begin, ntiles);
-    }
+    k_hop<SF, SY, CT, MODE, kHopNTP, SC><<<grid, block, 0, s>>>(g, sm, (const PC*)Uk, (const PC*)Cl, (const PF*)X,
+                                                             (const PF*)Rh, (PY*)Y, col_begin, ntiles);
     return hipGetLastError();
 }
 

@@ -4,7 +4,6 @@
 #pragma once
 
 #include <hip/hip_runtime.h>
-#include <cstdlib>
 #include <cstddef>
 #include <cstdint>
 
@@ -229,16 +228,9 @@ __device__ __forceinline__ int map_site(const Geom& g, const SiteMap& m, int b, 
 inline SiteMap make_site_map(const Geom& g, double bytes_site) {
     SiteMap m{};
     const double budget = 2.0 * 1024 * 1024;
-    // WDSOLVE_HOP_NY (tuning only) forces the y split when the lattice allows it
-    static const int forced_ny = [] {
-        const char* e = std::getenv("WDSOLVE_HOP_NY");
-        const int v = e ? std::atoi(e) : 0;
-        return (v == 1 || v == 2 || v == 4 || v == 8) ? v : 0;
-    }();
     for (int ny = 1; ny <= 8; ny *= 2) {
         const int nz = 8 / ny;
         if (g.ly < ny || g.lz < nz) continue;
-        if (forced_ny && ny != forced_ny && g.ly >= forced_ny && g.lz >= 8 / forced_ny) continue;
         const int rows = (g.ly + ny - 1) / ny;
         m.mode = 1;
         m.ny = ny;
@@ -346,6 +338,17 @@ hipError_t launch_gram_partials(const double2* P, const double2* Q, size_t N, in
 // reduce partials -> C (L x L row-major) on the device
 hipError_t launch_reduce_gram(const double2* partial, int nb, int L, double2* C, hipStream_t s);
 hipError_t launch_small_solve(const double2* M, const double2* RHS, int L, double2* Z, int* status, hipStream_t s);
+// Z = M^{-1} (c RHS); status_bit 0: *status = ok ? 0 : 1, else *status |= status_bit on failure;
+// cond (may be null): pivot-ratio condition estimate of M
+hipError_t launch_small_solve_scaled(const double2* M, const double2* RHS, int L, double2 c, double2* Z, int* status,
+                                     int status_bit, double* cond, hipStream_t s);
+// out = a A + b B + (c C + d D) M (N x L blocks, L x L matrix M; see k_block_comb)
+hipError_t launch_block_comb(double2* out, const double2* A, const double2* Bm, const double2* C, const double2* D,
+                             const double2* M, double2 a, double2 b, double2 c, double2 d, const double2* w, int wmask,
+                             size_t N, int L, hipStream_t s);
+// omega = Tr[Cts] / Tr[Ctt]
+hipError_t launch_stab_omega(const double2* Cts, const double2* Ctt, int L, double2* omega, int* status, int bit,
+                             hipStream_t s);
 
 // solver-specific fused kernels
 struct SolverBufs {
@@ -356,6 +359,7 @@ struct SolverBufs {
     double2* zeta;     // [0] = zeta, [1] = Tr W^H R, [2] = Tr W^H W
     double* norms;     // L squared column norms of R_{k+1}
     int* status;       // breakdown / nan flags
+    double* cond;      // [0]: condition estimate of Rt^H V_k, [1]: of Rt^H R_k
 };
 hipError_t launch_gram1(const double2* Rt, const double2* V, const double2* W, const double2* R, size_t N, int L,
                         double2* partial, int nb, hipStream_t s);

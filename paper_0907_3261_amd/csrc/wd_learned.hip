@@ -9,7 +9,6 @@
 // dl/dRe W_d + i dl/dIm W_d = 2 sum_{x,c,i} g(x) (S_d z)(x)^dag, the loss
 // mean_i ||y_i - e_i||^2 / ||e_i||^2 with its gradient, and Adam.
 #include <cmath>
-#include <cstdlib>
 #include <complex>
 #include <cstring>
 #include <vector>
@@ -367,31 +366,15 @@ hipError_t launch_layer_ct(const wd_ctx* c, const typename SL::P* U, const float
     return hipGetLastError();
 }
 
-// One layer over L columns: tiles of CT columns, then single columns for the rest.
-// Columns per thread: WDSOLVE_LEARN_CT (1, 2 or 4) if set, else 1.  At 32^3 x 64 with
-// twelve columns one column per thread is the fastest in both precisions (the wider tiles
-// lose occupancy to their accumulators and operand sets, and spill).
-inline int layer_ct(bool f64) {
-    static const int env = [] {
-        const char* e = std::getenv("WDSOLVE_LEARN_CT");
-        const int v = e ? std::atoi(e) : 0;
-        return (v == 1 || v == 2 || v == 4) ? v : 0;
-    }();
-    (void)f64;
-    return env ? env : 1;
-}
+// One layer over L columns, one column per thread.  At 32^3 x 64 with twelve
+// columns this is the fastest tiling in both precisions (two- and four-column
+// tiles lose occupancy to their accumulators and operand sets, and spill).
+constexpr int kLayerCT = 1;
 
 template <class SI, class SO, class SL>
 hipError_t launch_layer(const wd_ctx* c, const typename SL::P* U, const float2* W, const void* in, void* out, int L,
                         hipStream_t s) {
-    const int ct = layer_ct(sizeof(typename SL::R) == 8);
-    const int nt = L / ct;
-    hipError_t e = hipSuccess;
-    if (ct == 4) e = launch_layer_ct<SI, SO, SL, 4>(c, U, W, in, out, 0, nt, s);
-    else if (ct == 2) e = launch_layer_ct<SI, SO, SL, 2>(c, U, W, in, out, 0, nt, s);
-    else e = launch_layer_ct<SI, SO, SL, 1>(c, U, W, in, out, 0, nt, s);
-    if (e == hipSuccess) e = launch_layer_ct<SI, SO, SL, 1>(c, U, W, in, out, nt * ct, L - nt * ct, s);
-    return e;
+    return launch_layer_ct<SI, SO, SL, kLayerCT>(c, U, W, in, out, 0, L / kLayerCT, s);
 }
 
 template <class SI, class SO>

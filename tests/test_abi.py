@@ -69,6 +69,11 @@ def test_argument_checks_without_gpu(lib):
     assert not h.value
     assert L.wd_create(None, (c_int * 4)(4, 4, 4, 4), 0, 4, None) == -1
     assert L.wd_destroy(None) == -1
+    info = pkg._binding.SolveInfo()
+    info.status = 123
+    for solve in (L.bbicggr_solve, L.bbicgstab_solve):
+        assert solve(None, None, None, 4, 1e-12, None, ctypes.byref(info)) == -1
+    assert info.status == 123                         # argument errors leave info untouched
 
 
 def test_header_is_plain_c99_and_links(tmp_path, lib):
@@ -109,7 +114,7 @@ def test_struct_layouts_match_header():
         body = re.sub(r"/\*.*?\*/", "", body, flags=re.S)
         fields = re.findall(r"(\w+)(?:\[\w+\])?\s*;", body)
         assert fields == [f for f, _ in cls._fields_]
-    assert ctypes.sizeof(SolveInfo) == 7 * 4 + 4 + 8 * 2 + 8 + 8 + 2 * 16 * 8
+    assert ctypes.sizeof(SolveInfo) == 7 * 4 + 4 + 8 * 2 + 8 + 8 + 2 * 16 * 8 + 8 + 2 * 4
 
 
 def test_binding_constants_match_header():

@@ -2,7 +2,8 @@
 3.3), for L = 1 .. 12 right-hand sides, through the C ABI.
 
 Each solve must reach a true residual <= 1e-12 per column, recomputed with
-the oracle's operator on the whole lattice.  Without restarts the cost count
+the oracle's operator on the whole lattice; a run that loses rank and fails
+is continued on the halves of its block.  Without restarts or splits the cost count
 must equal 2(j+1)k + 1 applications per column, the relation every entry of
 Table 1 satisfies.  Iteration counts on these synthetic links are recorded
 (the paper's numbers need its gauge ensemble, so they are not compared).
@@ -65,19 +66,17 @@ def test_point_source_solve_l_sweep(setup, L):
     X, info = c.solve(torch.from_numpy(B).cuda(), tol=1e-12, j=j, stagnate_window=3000, max_iter=20000)
     _say(f"L={L}: {info['status']} k={info['iterations']} restarts={info['restarts']}")
     _record(f"L{L}", {"status": info["status"], "iterations": info["iterations"], "restarts": info["restarts"],
+                      "total_iterations": info["total_iterations"], "splits": info["splits"],
+                      "min_block": info["min_block"], "cond_max": info["cond_max"],
                       "mvm_paper_per_col": int(info["mvm_paper"]), "s_per_rhs": info["seconds"] / L})
-    if L < 4 and info["status"] in ("diverged", "stagnated"):
-        # with one to three sources this ensemble sits close enough to the critical kappa that
-        # block BiCGGR can wander off (the paper's Table 1 has such failures too); the solver
-        # must say so, and the true residual it reports must be that of the X it returns
-        tr = true_residual(op.A_mat, op.block_to_mat(B), op.block_to_mat(X.cpu().numpy()))
-        np.testing.assert_allclose(info["true_residual"][:L], tr, rtol=1e-6)
-        return
+    # with one to three sources this ensemble sits close to the critical kappa and a block run can
+    # lose rank and diverge (the paper's Table 1 has such failures too); the driver then solves
+    # the halves of the block on their own (Sec. 3.3), so every width must converge
     assert info["status"] == "converged", info
     tr = true_residual(op.A_mat, op.block_to_mat(B), op.block_to_mat(X.cpu().numpy()))
     assert np.max(tr) <= 1e-12
     np.testing.assert_allclose(info["true_residual"][:L], tr, rtol=0.05, atol=1e-15)  # both are rounding-limited
-    if info["restarts"] == 0:
+    if info["restarts"] == 0 and info["splits"] == 0:
         assert info["mvm_paper"] == 2 * (j + 1) * info["iterations"] + 1
     _REC[f"L{L}"]["true_residual_max"] = float(np.max(tr))
     _record(f"L{L}", _REC[f"L{L}"])

@@ -312,8 +312,8 @@ def test_solve_failure_paths(pkg):
     c = _ctx(pkg, dims, U, 0.12, 1.0)
     V = wi.volume(dims)
     b = wi.z4_block(V, 1, 131)
-    X, info = c.solve(_dev(np.concatenate([b, b])), j=1)
-    assert info["status"] == "breakdown"
+    X, info = c.solve(_dev(np.concatenate([b, b])), j=1, no_split=True)
+    assert info["status"] == "breakdown" and info["splits"] == 0
     assert np.all(np.isfinite(_host(X)))
     Bz = wi.z4_block(V, 2, 132)
     Bz[1] = 0
@@ -321,8 +321,11 @@ def test_solve_failure_paths(pkg):
         c.solve(_dev(Bz))
     X, info = c.solve(_dev(wi.z4_block(V, 2, 133)), j=0, max_iter=3, max_restarts=0)
     assert info["status"] == "not_converged" and info["iterations"] == 3
-    X, info = c.solve(_dev(wi.z4_block(V, 2, 133)), j=0, diverge_at=1e-3)
-    assert info["status"] == "diverged"
+    X, info = c.solve(_dev(wi.z4_block(V, 2, 133)), j=0, diverge_at=1e-3, no_split=True, max_restarts=0)
+    assert info["status"] == "diverged" and info["splits"] == 0
+    # with splitting the halves diverge as well, and the solve says so
+    X, info = c.solve(_dev(wi.z4_block(V, 2, 133)), j=0, diverge_at=1e-3, max_restarts=0)
+    assert info["status"] == "diverged" and info["splits"] == 1 and info["min_block"] == 1
     c.close()
 
 
