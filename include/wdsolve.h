@@ -272,6 +272,19 @@ int wd_block_gram(wd_ctx* ctx, const void* P, const void* Q, int L, void* C);
  * not finite. */
 int wd_small_solve(wd_ctx* ctx, const void* M, const void* RHS, int L, void* Z);
 
+/* C = P^H Q as wd_block_gram computes it, for callers that cannot allocate
+ * device memory (code under HIP graph capture, serving loops, hosts that
+ * forbid hipMalloc): no context, no allocation.  P and Q are device block
+ * vectors of N rows and L columns (column-major, N >= 1, 1 <= L <= WD_MAX_L),
+ * C an L x L row-major complex128 device matrix; all are owned by the caller.
+ * The reduction partials live in a fixed 2.2 MB device array of the library
+ * (one per GPU, kept until the process ends, enough for any N); calls that
+ * overlap on one GPU share it and race, so issue them one at a time.  Work
+ * goes on hip_stream (NULL: the default stream) and the call returns after it
+ * is complete.  Errors: WD_EINVAL (null pointer, N < 1, L out of range),
+ * WD_EHIP. */
+int wd_block_gram_static(const void* P, const void* Q, long long N, int L, void* C, void* hip_stream);
+
 /* ---------------------------------------------------------------------------
  * Learned preconditioner (linear, gauge covariant, frozen after training)
  * ------------------------------------------------------------------------- */

@@ -84,6 +84,7 @@ SIGNATURES = [
     ("wd_hop_repeat", c_int, [c_void_p, c_void_p, c_void_p, c_void_p, c_int, c_int, c_int, c_int]),
     ("wd_block_gram", c_int, [c_void_p, c_void_p, c_void_p, c_int, c_void_p]),
     ("wd_small_solve", c_int, [c_void_p, c_void_p, c_void_p, c_int, c_void_p]),
+    ("wd_block_gram_static", c_int, [c_void_p, c_void_p, c_longlong, c_int, c_void_p, c_void_p]),
     ("wd_set_learned", c_int, [c_void_p, c_void_p]),
     ("wd_learned_init", c_int, [c_void_p, c_int]),
     ("wd_learned_pairs", c_int, [c_void_p, c_void_p, c_void_p, c_void_p, c_int, c_int, c_void_p, c_void_p]),
@@ -348,6 +349,15 @@ class Context:
         L = P.shape[0]
         C = torch.empty((L, L), dtype=torch.complex128, device=self.device)
         _check(self._lib.wd_block_gram(self._h, self._block(P), self._block(Q, L), L, _dptr(C)), "wd_block_gram")
+        return C
+
+    def gram_static(self, P, Q):
+        """P^H Q through the entry point that allocates nothing (no context workspace)."""
+        torch = _torch()
+        L = P.shape[0]
+        C = torch.empty((L, L), dtype=torch.complex128, device=self.device)
+        _check(self._lib.wd_block_gram_static(self._block(P), self._block(Q, L), self.N, L, _dptr(C),
+                                              c_void_p(self.stream.cuda_stream)), "wd_block_gram_static")
         return C
 
     def small_solve(self, M, RHS):

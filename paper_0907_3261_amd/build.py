@@ -19,7 +19,7 @@ CSRC = os.path.join(PKG, "csrc")
 BUILD = os.path.join(ROOT, "_build")
 LIB = os.path.join(PKG, "libwdsolve.so")
 
-SOURCES = ["wd_setup.hip", "wd_dslash.hip", "wd_blas.hip", "wd_learned.hip", "wd_api.hip"]
+SOURCES = ["wd_setup.hip", "wd_dslash.hip", "wd_blas.hip", "wd_learned.hip", "wd_api.hip", "wd_noalloc.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = [
