@@ -67,6 +67,9 @@ def parse():
     p.add_argument("--ensembles", type=int, default=0,
                    help="compare the preconditioner precisions over this many link ensembles (link seeds) "
                         "at --kappa and --kappa-heavy: converged counts and mean s/RHS")
+    p.add_argument("--conditioning", action="store_true",
+                   help="only the conditioning probe: power iteration of kappa T^-1 H and ARPACK's leftmost "
+                        "eigenvalues of A (GPU operator as the matrix-vector product) per lattice and kappa")
     p.add_argument("--kernels-only", action="store_true",
                    help="only the hopping-kernel launches and a plain copy (for rocprofv3 counter runs)")
     return p.parse_args()
@@ -322,6 +325,74 @@ def ensemble_sweep(pkg, wi, torch, np, w, a, kappa, L, V, B):
     return {"ensembles": summary, "workload": a.workload, "L": L, "j": a.j, "runs": runs}
 
 
+def conditioning_probe(pkg, wi, torch, np, kappas=(0.120, 0.127, 0.130, 0.135)):
+    """How close each synthetic ensemble is to its critical kappa, the analogue of the paper's
+    kappa against kappa_c (Sec. 3.1).  Per lattice and kappa:
+      rho   spectral radius of E = kappa T^-1 H, the Jacobi iteration matrix of the block reading
+            (the sweep with zero right-hand side applies exactly E), from 300 power steps on one
+            column: the geometric mean of the last 100 norm ratios;
+      eig   the four eigenvalues of A with the smallest real part (ARPACK 'SR' through scipy, the
+            GPU operator as its matrix-vector product) on the smallest lattice, where the host side
+            of ARPACK stays cheap."""
+    import scipy.sparse.linalg as sla
+    out = {}
+    for name in ("lat8x16_L12_point", "lat16x32_point", "lat32x64_L12_point"):
+        w = wi.workload(name)
+        V = wi.volume(w["dims"])
+        N = 12 * V
+        U = wi.random_links(w["dims"], w["eps"], w["link_seed"])
+        ctx = pkg.Context(w["dims"], bc_t=w["bc_t"], max_L=1)
+        ctx.set_links(U)
+        del U
+        g = torch.Generator(device="cuda").manual_seed(21)
+        X0 = torch.complex(torch.randn((1, 12, V), generator=g, device="cuda", dtype=torch.float64),
+                           torch.randn((1, 12, V), generator=g, device="cuda", dtype=torch.float64))
+        Z = torch.zeros_like(X0)
+        Y = torch.empty_like(X0)
+        for kp in kappas:
+            ctx.set_params(kp, w["csw"])
+            X = X0 / torch.linalg.vector_norm(X0)
+            logs = []
+            for _ in range(300):
+                ctx.hop_repeat(X, Y, 1, mode=1, R=Z)
+                nrm = float(torch.linalg.vector_norm(Y))
+                logs.append(np.log(nrm))
+                X = Y / nrm
+            rec = {"rho_kappaTinvH": round(float(np.exp(np.mean(logs[-100:]))), 5)}
+            if N <= 200_000:
+                Xd = ctx.empty_block(1)
+                Yd = ctx.empty_block(1)
+
+                count = [0]
+
+                def mv(v):
+                    Xd.copy_(torch.from_numpy(np.ascontiguousarray(v.reshape(1, 12, V))))
+                    ctx.apply(Xd, Yd)
+                    count[0] += 1
+                    if count[0] % 1000 == 0:
+                        print(f"[bench] conditioning {name} kappa={kp}: {count[0]} products", file=sys.stderr,
+                              flush=True)
+                    return Yd.cpu().numpy().reshape(-1)
+
+                Aop = sla.LinearOperator((N, N), matvec=mv, dtype=np.complex128)
+                t0 = time.time()
+                try:
+                    ev = sla.eigs(Aop, k=4, which="SR", ncv=40, tol=1e-5, maxiter=2000,
+                                  return_eigenvectors=False)
+                    ev = np.sort_complex(ev)
+                    rec["eig_smallest_real"] = [[round(float(e.real), 5), round(float(e.imag), 5)] for e in ev]
+                    rec["min_re"] = round(float(ev.real.min()), 5)
+                except sla.ArpackNoConvergence as e:
+                    rec["eig_smallest_real"] = "ARPACK did not converge"
+                rec["arpack_s"] = round(time.time() - t0, 1)
+                rec["arpack_products"] = count[0]
+            out[f"{name}_kappa{kp}"] = rec
+            print(f"[bench] conditioning {name} kappa={kp}: {rec}", file=sys.stderr, flush=True)
+        ctx.close()
+        torch.cuda.empty_cache()
+    return out
+
+
 def cpu_baseline(w, kappa):
     """Oracle A X on a 32 x 32 x 32 x 2 slab of the workload's ensemble, twelve columns."""
     import numpy as np
@@ -359,6 +430,9 @@ def main():
     import wdinputs as wi
 
     pkg.load()
+    if a.conditioning:
+        print(json.dumps({"conditioning": conditioning_probe(pkg, wi, torch, np)}), flush=True)
+        return
     w = wi.workload(a.workload)
     # solves run at the workload's subcritical kappa_solve when its nominal kappa is past criticality
     kappa = a.kappa if a.kappa is not None else w.get("kappa_solve", w["kappa"])
