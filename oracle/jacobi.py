@@ -48,3 +48,4 @@ def jacobi_apply(op, U: np.ndarray, j: int, G0: np.ndarray | None = None) -> np.
 def jacobi_mat(op, m: np.ndarray, j: int) -> np.ndarray:
     """M applied to an N x L matrix in the oracle's row order."""
     return op.to_matrix(jacobi_apply(op, op.from_matrix(m), j))
+

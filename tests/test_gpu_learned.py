@@ -105,7 +105,7 @@ def test_gradient_matches_oracle(pkg, L):
     lo, Go = ln.grad(op, th, op.from_block(R), op.from_block(E))
     _say(f"grad L={L}: loss {lv:.6e} vs {lo:.6e}, G maxrel {_maxrel(G, Go):.2e}")
     assert abs(lv - lo) / lo < 1e-5
-    assert _maxrel(G, Go) < 1e-4
+    assert _maxrel(G, Go) < 1e-5
     c.close()
 
 

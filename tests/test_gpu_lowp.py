@@ -20,6 +20,17 @@ format: 2^-24 for FP32, 2^-8 for BF16 with round-to-nearest-even):
   each product of a sweep carries the rounding of one stored factor (u), so
   half the bound of the rounded-vector form per sweep, 4.5 u; and the map is
   linear to FP64 rounding, which the rounded-vector form is not.
+* against the oracle's emulation of the same storage (``oracle.lowp``: the same
+  rounded links, site matrices, inputs and stored iterates, float32 arithmetic
+  in numpy's order) only the order of the float32 operations differs: an
+  application then agrees to ~sqrt(100) u32 of the sum of |terms| (measured
+  ~1e-7; bound 1e-6 relative to the largest output), in FP32 and in BF16
+  alike, since BF16 rounds the inputs but not the result; a j-step FP32
+  Jacobi stays within 2e-6 (the sweeps contract, so order differences do not
+  grow with j); a BF16 Jacobi with j >= 2 rounds its iterates, and an order
+  difference near a BF16 rounding boundary flips an element by one BF16 ulp
+  (2^-8 of itself) now and then, so there the bound is 2^-7 of the largest
+  element and 5e-4 in the Frobenius norm.
 * solves: X and R are updated in FP64 from F = M R and G = M U, and W = A F,
   Y = A G are formed in FP64 (Sec. 2, algorithm box), so any M -- however
   inexact -- only changes the iteration count: the true residual must still
@@ -37,6 +48,7 @@ import wdinputs as wi
 from oracle import WilsonClover
 from oracle.jacobi import jacobi_apply
 from oracle.bbicggr import true_residual
+from oracle.lowp import apply_lowp, jacobi_sweeps_lowp
 
 pytestmark = pytest.mark.gpu
 torch = pytest.importorskip("torch")
@@ -88,6 +100,36 @@ def test_apply_lowp(pkg, prec, L):
     err = _maxrel(Y, op.to_block(op.apply_A(op.from_block(X))))
     _record(f"apply_{prec}_L{L}", err)
     assert err < APPLY_TOL[prec]
+    c.close()
+
+
+@pytest.mark.parametrize("prec", ["f32", "bf16"])
+@pytest.mark.parametrize("L", [1, 12])
+def test_apply_lowp_against_emulated_storage(pkg, prec, L):
+    c, op = _setup(pkg)
+    X = wi.gaussian_block(op.V, L, 306)
+    Y = c.apply(torch.from_numpy(X).cuda(), prec=prec).cpu().numpy()
+    err = _maxrel(Y, op.to_block(apply_lowp(op, op.from_block(X), prec)))
+    _record(f"apply_{prec}_L{L}_vs_emulated", err)
+    assert err < 1e-6
+    c.close()
+
+
+@pytest.mark.parametrize("prec", ["f32", "bf16"])
+@pytest.mark.parametrize("j,L", [(1, 4), (2, 4), (12, 4), (3, 12)])
+def test_jacobi_lowp_against_emulated_storage(pkg, prec, j, L):
+    c, op = _setup(pkg)
+    R = wi.gaussian_block(op.V, L, 307)
+    Z = c.jacobi(torch.from_numpy(R).cuda(), j, prec=prec).cpu().numpy()
+    Zo = op.to_block(jacobi_sweeps_lowp(op, op.from_block(R), j, prec))
+    err = _maxrel(Z, Zo)
+    nrm = np.linalg.norm(Z - Zo) / np.linalg.norm(Zo)
+    _record(f"jacobi_{prec}_j{j}_L{L}_vs_emulated", err)
+    _record(f"jacobi_{prec}_j{j}_L{L}_vs_emulated_frobenius", nrm)
+    if prec == "f32" or j == 1:
+        assert err < 2e-6
+    else:
+        assert err < 2.0 ** -7 and nrm < 5e-4
     c.close()
 
 
