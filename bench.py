@@ -529,8 +529,9 @@ def main():
     # learned M, at the workload's kappa and at a heavier quark mass (kappa_heavy)
     # the low-precision sweep of the mixed-precision Jacobi (FP32 accumulate)
     lowp = {}
-    for prec, per_site in (("f32", 576 + 288 * L), ("bf16", 288 + 144 * L),
-                           ("f64c32", 576 + 576 * L), ("f64cbf16", 288 + 576 * L)):
+    # FP32 / BF16 links are stored as two rows (192 / 96 B per site), T^-1 in full (288 / 144 B)
+    for prec, per_site in (("f32", 480 + 288 * L), ("bf16", 240 + 144 * L),
+                           ("f64c32", 480 + 576 * L), ("f64cbf16", 240 + 576 * L)):
         ms_p = time_hop(ctx, torch, V, L, 1, a.hop_reps, prec)
         b_p = V * per_site
         lowp[prec] = {"avg_launch_ms": round(ms_p, 4), "alg_bytes_per_launch": b_p,

@@ -10,7 +10,12 @@ library uses):
 
 * rounding is round-to-nearest-even, FP64 -> FP32 by the float32 cast and
   FP32 -> BF16 by dropping 16 bits after adding the tie-breaking bias;
-* what is stored: kappa U_mu (scaled in FP64, then rounded), T and T^{-1}
+* links in FP32 and BF16 are stored as their first two rows only, rows 0
+  and 1 of kappa U_mu (scaled in FP64, then rounded); the third row is
+  rebuilt in float32 as conj(r_0 x r_1) / kappa, which is kappa times the
+  third row of an SU(3) matrix (unitary, unit determinant), and is not
+  rounded to the storage format;
+* what else is stored: T and T^{-1}
   (built and inverted in FP64, then rounded), the input spinor field, and
   in a j-step Jacobi application the right-hand side and the iterates
   G_1 .. G_{j-1}; the final result is returned unrounded;
@@ -55,6 +60,11 @@ class LowpOperator:
         self.op = op
         self.fmt = fmt
         self.links = [store(op.kappa * op.U[mu], fmt) for mu in range(4)]
+        if fmt != "f64":
+            invk = np.float32(1.0 / op.kappa) if op.kappa != 0 else np.float32(0.0)
+            for lk in self.links:
+                r0, r1 = lk[..., 0, :], lk[..., 1, :]
+                lk[..., 2, :] = np.conj(np.cross(r0, r1)) * invk
         self.T = store(op.T, fmt)
         self.Tinv = store(op.Tinv, fmt)
         cdt = np.complex128 if fmt == "f64" else np.complex64

@@ -240,6 +240,7 @@ int wd_set_params(wd_ctx* c, double kappa, double csw, int jacobi_kind) {
     if (!std::isfinite(kappa) || !std::isfinite(csw)) return WD_EINVAL;
     if (jacobi_kind != WD_JACOBI_BLOCK && jacobi_kind != WD_JACOBI_POINT) return WD_EINVAL;
     const size_t V = c->g.V, links = (size_t)36 * V, clov = (size_t)36 * V;
+    const size_t psize[3] = {16, 8, 4};
     hipStream_t s = c->stream;
     double2* Ti64 = (double2*)c->f.Ti[0];
     WD_TRY_HIP(launch_clover(c->f.U, c->f.T, Ti64, c->g, kappa, csw, s));
@@ -248,7 +249,11 @@ int wd_set_params(wd_ctx* c, double kappa, double csw, int jacobi_kind) {
     WD_TRY_HIP(launch_convert(c->f.T, c->f.Tc[0], Prec::F64, 1.0, clov, s));
     for (int p = 1; p < 3; ++p) {
         const Prec pr = (Prec)p;
-        WD_TRY_HIP(launch_convert(c->f.U, c->f.Uk[p], pr, kappa, links, s));
+        // FP32 / BF16 links keep their first two rows (planes [mu][6][V]); the hop kernels
+        // rebuild the third from them
+        for (int mu = 0; mu < 4; ++mu)
+            WD_TRY_HIP(launch_convert(c->f.U + (size_t)mu * 9 * V, (char*)c->f.Uk[p] + (size_t)mu * 6 * V * psize[p], pr,
+                                      kappa, (size_t)6 * V, s));
         WD_TRY_HIP(launch_convert(Ti64, c->f.Ti[p], pr, 1.0, clov, s));
         WD_TRY_HIP(launch_convert((const double2*)c->f.Tp[0], c->f.Tp[p], pr, 1.0, clov, s));
         WD_TRY_HIP(launch_convert(c->f.T, c->f.Tc[p], pr, 1.0, clov, s));
@@ -438,15 +443,26 @@ struct Solver {
         if (precond == WD_PRECOND_JACOBI && j > 0 && coef) {
             WD_TRY_HIP(launch_jacobi_coef(c, in, out, L, j, (Prec)coef, c->stream));
             mvm_actual += (long long)(j - 1) * L;
-            // FP64 vectors; links (576 B per site in FP64) and A_D^{-1} (576 B) at 1/2 or 1/4
+            // FP64 vectors; A_D^{-1} (576 B per site in FP64) at 1/2 or 1/4, the links as two of
+            // their three rows (384 B at FP64 size) at 1/2 or 1/4
             const double cs = coef == (int)Prec::F32 ? 0.5 : 0.25;
-            bytes += (double)c->g.V * (bytes_first_sweep(L) - 576.0 * (1.0 - cs) +
-                                       (j - 1) * (bytes_sweep(L) - 1152.0 * (1.0 - cs)));
+            bytes += (double)c->g.V * (576.0 * cs + 384.0 * L + (j - 1) * (960.0 * cs + 576.0 * L));
+        } else if (precond == WD_PRECOND_JACOBI && j > 0 && pin != Prec::F64) {
+            WD_TRY_HIP(launch_jacobi(c, in, out, L, j, pin, c->stream));
+            mvm_actual += (long long)(j - 1) * L;
+            // s: storage size relative to FP64.  The first sweep reads the FP64 right-hand side and
+            // stores its rounded copy and G_1; the middle sweeps read and write storage format;
+            // the last writes FP64 (j = 1: FP64 in, FP64 out).
+            const double s = pin == Prec::F32 ? 0.5 : 0.25, Lf = L;
+            const double coefs = 960.0 * s;  // two-row links and A_D^{-1}
+            bytes += (double)c->g.V *
+                     (j == 1 ? 576.0 * s + 384.0 * Lf
+                             : (576.0 * s + 192.0 * Lf + 384.0 * Lf * s) + (j - 2) * (coefs + 576.0 * Lf * s) +
+                                   (coefs + 384.0 * Lf * s + 192.0 * Lf));
         } else if (precond == WD_PRECOND_JACOBI && j > 0) {
             WD_TRY_HIP(launch_jacobi(c, in, out, L, j, pin, c->stream));
             mvm_actual += (long long)(j - 1) * L;
-            const double scale = pin == Prec::F64 ? 1.0 : (pin == Prec::F32 ? 0.5 : 0.25);
-            bytes += (double)c->g.V * (bytes_first_sweep(L) + (j - 1) * bytes_sweep(L)) * scale;
+            bytes += (double)c->g.V * (bytes_first_sweep(L) + (j - 1) * bytes_sweep(L));
         } else {
             WD_TRY_HIP(launch_copy(out, in, N * L, c->stream));
             blocks(2);

@@ -133,24 +133,55 @@ __device__ __forceinline__ void hop_dir(cx<R> (&acc)[12], const cx<R> (&u)[9], c
     }
 }
 
+// Links stored in FP32 or BF16 keep only their first two rows (12 reals,
+// "reconstruct-12"): for U in SU(3) the third row is the complex conjugate of
+// the cross product of the first two.  The stored rows carry kappa, so the
+// product carries kappa^2 and is scaled by 1/kappa; a link whose sign was
+// flipped for the antiperiodic time boundary has its first two rows flipped,
+// which leaves their cross product unchanged, so the third row is negated
+// there (neg).
+template <class SC>
+constexpr bool kCompressedLinks = sizeof(typename SC::P) < 16;
+
+template <typename R>
+__device__ __forceinline__ void third_row(cx<R> (&u)[9], R invk, bool neg) {
+    const R f = neg ? -invk : invk;
+#pragma unroll
+    for (int b = 0; b < 3; ++b) {
+        const int b1 = (b + 1) % 3, b2 = (b + 2) % 3;
+        const cx<R> w = u[b1] * u[3 + b2] - u[b2] * u[3 + b1];
+        u[6 + b] = {f * w.re, -f * w.im};
+    }
+}
+
 // One hop direction for the CT columns of this thread: the link is loaded
 // once and applied to every column.  Xc is the wave-uniform base of the
 // thread's first column; link_off and nb_off are byte offsets of the link's
 // site and of the neighbour site inside one plane.  SC: storage of the links
-// (widened to the compute type of S on load).
+// (widened to the compute type of S on load; FP32 and BF16 links are stored
+// as two rows, planes [mu][6][V], and completed by third_row).
 template <class S, int MU, bool FWD, bool ADD, int CT, bool NT = false, class SC = S>
 __device__ __forceinline__ void hop_all(cx<typename S::R> (&acc)[CT][12], const typename SC::P* __restrict__ Uk,
                                         const typename S::P* __restrict__ Xc, uint32_t link_off, uint32_t nb_off,
-                                        size_t V) {
+                                        size_t V, typename S::R invk = 0, bool neg = false) {
     using R = typename S::R;
     // keep each direction's loads and arithmetic together: without this fence
     // the scheduler hoists the loads of all eight directions and spills
     __builtin_amdgcn_sched_barrier(0);
     cx<R> u[9];
+    if constexpr (kCompressedLinks<SC>) {
 #pragma unroll
-    for (int k = 0; k < 9; ++k) {
-        const cx<typename SC::R> v = SC::ldb(Uk + (size_t)(MU * 9 + k) * V, link_off);
-        u[k] = {(R)v.re, (R)v.im};
+        for (int k = 0; k < 6; ++k) {
+            const cx<typename SC::R> v = SC::ldb(Uk + (size_t)(MU * 6 + k) * V, link_off);
+            u[k] = {(R)v.re, (R)v.im};
+        }
+        third_row<R>(u, invk, neg);
+    } else {
+#pragma unroll
+        for (int k = 0; k < 9; ++k) {
+            const cx<typename SC::R> v = SC::ldb(Uk + (size_t)(MU * 9 + k) * V, link_off);
+            u[k] = {(R)v.re, (R)v.im};
+        }
     }
 #pragma unroll
     for (int c = 0; c < CT; ++c) {
@@ -176,7 +207,7 @@ template <class SF, class SY, int CT, int MODE, int NTP = 0, class SC = SF>
 __global__ void __launch_bounds__(256)
     k_hop(const Geom g, const SiteMap sm, const typename SC::P* __restrict__ Uk, const typename SC::P* __restrict__ Cl,
           const typename SF::P* __restrict__ X, const typename SF::P* __restrict__ Rh, typename SY::P* __restrict__ Y,
-          const int col_begin, const int ntiles) {
+          const int col_begin, const int ntiles, const double invk_d, const int bc_t) {
     using R = typename SF::R;
     using PF = typename SF::P;
     using PY = typename SY::P;
@@ -240,14 +271,18 @@ __global__ void __launch_bounds__(256)
     }
 
     constexpr bool ADD = (MODE != APPLY);
-    hop_all<SF, 0, true, ADD, CT, false, SC>(acc, Uk, Xc, co(o_s), o_fx, V);
-    hop_all<SF, 0, false, ADD, CT, false, SC>(acc, Uk, Xc, co(o_bx), o_bx, V);
-    hop_all<SF, 1, true, ADD, CT, false, SC>(acc, Uk, Xc, co(o_s), o_fy, V);
-    hop_all<SF, 1, false, ADD, CT, false, SC>(acc, Uk, Xc, co(o_by), o_by, V);
-    hop_all<SF, 2, true, ADD, CT, false, SC>(acc, Uk, Xc, co(o_s), o_fz, V);
-    hop_all<SF, 2, false, ADD, CT, false, SC>(acc, Uk, Xc, co(o_bz), o_bz, V);
-    hop_all<SF, 3, true, ADD, CT, (NTP & 2) != 0, SC>(acc, Uk, Xc, co(o_s), o_ft, V);
-    hop_all<SF, 3, false, ADD, CT, (NTP & 2) != 0, SC>(acc, Uk, Xc, co(o_bt), o_bt, V);
+    // compressed links: 1/kappa, and the antiperiodic sign of the time links on the last slice
+    // (the forward link of t = Lt - 1, the backward link seen from t = 0)
+    const R invk = (R)invk_d;
+    const bool neg_ft = bc_t && t == g.lt - 1, neg_bt = bc_t && t == 0;
+    hop_all<SF, 0, true, ADD, CT, false, SC>(acc, Uk, Xc, co(o_s), o_fx, V, invk);
+    hop_all<SF, 0, false, ADD, CT, false, SC>(acc, Uk, Xc, co(o_bx), o_bx, V, invk);
+    hop_all<SF, 1, true, ADD, CT, false, SC>(acc, Uk, Xc, co(o_s), o_fy, V, invk);
+    hop_all<SF, 1, false, ADD, CT, false, SC>(acc, Uk, Xc, co(o_by), o_by, V, invk);
+    hop_all<SF, 2, true, ADD, CT, false, SC>(acc, Uk, Xc, co(o_s), o_fz, V, invk);
+    hop_all<SF, 2, false, ADD, CT, false, SC>(acc, Uk, Xc, co(o_bz), o_bz, V, invk);
+    hop_all<SF, 3, true, ADD, CT, (NTP & 2) != 0, SC>(acc, Uk, Xc, co(o_s), o_ft, V, invk, neg_ft);
+    hop_all<SF, 3, false, ADD, CT, (NTP & 2) != 0, SC>(acc, Uk, Xc, co(o_bt), o_bt, V, invk, neg_bt);
     __builtin_amdgcn_sched_barrier(0);
 
     PY* Yc = Y + (size_t)c0 * cs;
@@ -367,9 +402,16 @@ int tile_cols(int L, bool lowp) {
     return 4;
 }
 
+// What the compressed links need besides the field: 1/kappa and the time boundary condition.
+struct LinkInfo {
+    double invk;
+    int bc_t;
+};
+LinkInfo link_info(const wd_ctx* c) { return {c->kappa != 0.0 ? 1.0 / c->kappa : 0.0, c->bc_t}; }
+
 template <class SF, class SY, int MODE, int CT, class SC = SF>
-hipError_t launch_hop_ct(const Geom& g, const void* Uk, const void* Cl, const void* X, const void* Rh, void* Y,
-                         int col_begin, int ntiles, hipStream_t s) {
+hipError_t launch_hop_ct(const Geom& g, const LinkInfo& li, const void* Uk, const void* Cl, const void* X,
+                         const void* Rh, void* Y, int col_begin, int ntiles, hipStream_t s) {
     if (ntiles > 4) return hipErrorInvalidValue;  // at most 4 wavefronts (256 threads) per site tile
     const double bytes_site = 12.0 * CT * ntiles * sizeof(typename SF::P) + 72.0 * sizeof(typename SC::P);
     const SiteMap sm = make_site_map(g, bytes_site);
@@ -378,18 +420,19 @@ hipError_t launch_hop_ct(const Geom& g, const void* Uk, const void* Cl, const vo
     using PY = typename SY::P;
     using PC = typename SC::P;
     k_hop<SF, SY, CT, MODE, kHopNTP, SC><<<grid, block, 0, s>>>(g, sm, (const PC*)Uk, (const PC*)Cl, (const PF*)X,
-                                                             (const PF*)Rh, (PY*)Y, col_begin, ntiles);
+                                                             (const PF*)Rh, (PY*)Y, col_begin, ntiles, li.invk,
+                                                             li.bc_t);
     return hipGetLastError();
 }
 
 template <class SF, class SY, int MODE, class SC = SF>
-hipError_t launch_hop_cols(const Geom& g, const void* Uk, const void* Cl, const void* X, const void* Rh, void* Y,
-                           int CT, int col_begin, int ntiles, hipStream_t s) {
+hipError_t launch_hop_cols(const Geom& g, const LinkInfo& li, const void* Uk, const void* Cl, const void* X,
+                           const void* Rh, void* Y, int CT, int col_begin, int ntiles, hipStream_t s) {
     switch (CT) {
-        case 1: return launch_hop_ct<SF, SY, MODE, 1, SC>(g, Uk, Cl, X, Rh, Y, col_begin, ntiles, s);
-        case 2: return launch_hop_ct<SF, SY, MODE, 2, SC>(g, Uk, Cl, X, Rh, Y, col_begin, ntiles, s);
-        case 3: return launch_hop_ct<SF, SY, MODE, 3, SC>(g, Uk, Cl, X, Rh, Y, col_begin, ntiles, s);
-        case 4: return launch_hop_ct<SF, SY, MODE, 4, SC>(g, Uk, Cl, X, Rh, Y, col_begin, ntiles, s);
+        case 1: return launch_hop_ct<SF, SY, MODE, 1, SC>(g, li, Uk, Cl, X, Rh, Y, col_begin, ntiles, s);
+        case 2: return launch_hop_ct<SF, SY, MODE, 2, SC>(g, li, Uk, Cl, X, Rh, Y, col_begin, ntiles, s);
+        case 3: return launch_hop_ct<SF, SY, MODE, 3, SC>(g, li, Uk, Cl, X, Rh, Y, col_begin, ntiles, s);
+        case 4: return launch_hop_ct<SF, SY, MODE, 4, SC>(g, li, Uk, Cl, X, Rh, Y, col_begin, ntiles, s);
         default: return hipErrorInvalidValue;
     }
 }
@@ -397,17 +440,17 @@ hipError_t launch_hop_cols(const Geom& g, const void* Uk, const void* Cl, const 
 // L columns: launches of up to four tiles of CT columns, then one launch for
 // the remainder (fewer than CT columns).
 template <class SF, class SY, int MODE, class SC = SF>
-hipError_t launch_hop_t(const Geom& g, const void* Uk, const void* Cl, const void* X, const void* Rh, void* Y, int L,
-                        hipStream_t s) {
+hipError_t launch_hop_t(const Geom& g, const LinkInfo& li, const void* Uk, const void* Cl, const void* X,
+                        const void* Rh, void* Y, int L, hipStream_t s) {
     const int CT = tile_cols(L, sizeof(typename SF::P) < 16);
     const int full = L / CT, rem = L % CT;
     hipError_t e = hipSuccess;
     for (int t0 = 0; t0 < full && e == hipSuccess; t0 += 4) {
         const int nt = full - t0 < 4 ? full - t0 : 4;
-        e = launch_hop_cols<SF, SY, MODE, SC>(g, Uk, Cl, X, Rh, Y, CT, t0 * CT, nt, s);
+        e = launch_hop_cols<SF, SY, MODE, SC>(g, li, Uk, Cl, X, Rh, Y, CT, t0 * CT, nt, s);
     }
     if (e != hipSuccess || rem == 0) return e;
-    return launch_hop_cols<SF, SY, MODE, SC>(g, Uk, Cl, X, Rh, Y, rem, full * CT, 1, s);
+    return launch_hop_cols<SF, SY, MODE, SC>(g, li, Uk, Cl, X, Rh, Y, rem, full * CT, 1, s);
 }
 
 template <class SI, class SF, class SY, class SC = SF>
@@ -427,8 +470,8 @@ hipError_t launch_first(const wd_ctx* c, const void* Cl, const void* Rin, void* 
 template <class SF, class SY, class SC = SF>
 hipError_t launch_sweep(const wd_ctx* c, int pi, const void* X, const void* Rh, void* Y, int L, hipStream_t s) {
     if (c->jacobi_kind == WD_JACOBI_POINT)
-        return launch_hop_t<SF, SY, JPOINT, SC>(c->g, c->f.Uk[pi], c->f.Tp[pi], X, Rh, Y, L, s);
-    return launch_hop_t<SF, SY, JBLOCK, SC>(c->g, c->f.Uk[pi], c->f.Ti[pi], X, Rh, Y, L, s);
+        return launch_hop_t<SF, SY, JPOINT, SC>(c->g, link_info(c), c->f.Uk[pi], c->f.Tp[pi], X, Rh, Y, L, s);
+    return launch_hop_t<SF, SY, JBLOCK, SC>(c->g, link_info(c), c->f.Uk[pi], c->f.Ti[pi], X, Rh, Y, L, s);
 }
 
 // j sweeps with FP64 vectors and arithmetic and the links and A_D^{-1} of
@@ -468,7 +511,7 @@ hipError_t jacobi_lowp(wd_ctx* c, int pi, const double2* R, double2* Z, int L, i
 }  // namespace
 
 hipError_t launch_apply_A(const wd_ctx* c, const double2* X, double2* Y, int L, hipStream_t s) {
-    return launch_hop_t<StF64, StF64, APPLY>(c->g, c->f.Uk[0], c->f.T, X, nullptr, Y, L, s);
+    return launch_hop_t<StF64, StF64, APPLY>(c->g, link_info(c), c->f.Uk[0], c->f.T, X, nullptr, Y, L, s);
 }
 
 hipError_t launch_sweep_f64(const wd_ctx* c, const double2* X, const double2* R, double2* Y, int L, hipStream_t s) {
@@ -487,8 +530,9 @@ hipError_t launch_apply_A_lowp(wd_ctx* c, const double2* X, double2* Y, int L, P
     hipError_t e = launch_to_lowp(X, c->lp[0], p, n, s);
     if (e != hipSuccess) return e;
     if (p == Prec::F32)
-        return launch_hop_t<StF32, StF64, APPLY>(c->g, c->f.Uk[1], c->f.Tc[1], c->lp[0], nullptr, Y, L, s);
-    return launch_hop_t<StBF16, StF64, APPLY>(c->g, c->f.Uk[2], c->f.Tc[2], c->lp[0], nullptr, Y, L, s);
+        return launch_hop_t<StF32, StF64, APPLY>(c->g, link_info(c), c->f.Uk[1], c->f.Tc[1], c->lp[0], nullptr, Y, L,
+                                                 s);
+    return launch_hop_t<StBF16, StF64, APPLY>(c->g, link_info(c), c->f.Uk[2], c->f.Tc[2], c->lp[0], nullptr, Y, L, s);
 }
 
 hipError_t launch_jacobi_coef(wd_ctx* c, const double2* R, double2* Z, int L, int j, Prec coef, hipStream_t s) {
@@ -531,8 +575,10 @@ hipError_t launch_hop_repeat_lowp(wd_ctx* c, const double2* X, const double2* R,
     for (int i = 0; i < nrep && e == hipSuccess; ++i) {
         if (mode == 0)
             e = p == Prec::F32
-                    ? launch_hop_t<StF32, StF64, APPLY>(c->g, c->f.Uk[1], c->f.Tc[1], c->lp[0], nullptr, Y, L, s)
-                    : launch_hop_t<StBF16, StF64, APPLY>(c->g, c->f.Uk[2], c->f.Tc[2], c->lp[0], nullptr, Y, L, s);
+                    ? launch_hop_t<StF32, StF64, APPLY>(c->g, link_info(c), c->f.Uk[1], c->f.Tc[1], c->lp[0], nullptr,
+                                                        Y, L, s)
+                    : launch_hop_t<StBF16, StF64, APPLY>(c->g, link_info(c), c->f.Uk[2], c->f.Tc[2], c->lp[0],
+                                                         nullptr, Y, L, s);
         else
             e = p == Prec::F32 ? launch_sweep<StF32, StF32>(c, pi, c->lp[0], c->lp[2], c->lp[1], L, s)
                                : launch_sweep<StBF16, StBF16>(c, pi, c->lp[0], c->lp[2], c->lp[1], L, s);

@@ -398,7 +398,7 @@ def test_full_size_jacobi_two_sweeps_sampled(pkg, big):
         assert _maxrel(Zs[:, :, k].T, ref) < 1e-13
 
 
-@pytest.mark.parametrize("prec,tol", [("f32", 2e3 * 2.0 ** -24), ("bf16", 18 * 2.0 ** -8),
+@pytest.mark.parametrize("prec,tol", [("f32", 8e-6), ("bf16", 3e-2),
                                       ("f64c32", 9 * 2.0 ** -24), ("f64cbf16", 9 * 2.0 ** -8)])
 def test_full_size_jacobi_two_sweeps_sampled_low_precision(pkg, big, prec, tol):
     """The low-precision Jacobi kernels in the benchmark's launch configuration (32^3 x 64,

@@ -61,3 +61,13 @@ def test_low_formats_within_rounding_bounds(fmt, u):
         assert u / 100 < e < j * bound
     s = store(X, fmt)
     assert s.dtype == np.complex64 and np.array_equal(store(s, fmt), s)
+
+
+def test_third_row_of_links_is_conjugate_cross_product():
+    """The synthetic links exp(i eps H), H traceless Hermitian, lie in SU(3): unitary with unit
+    determinant, so row 2 = conj(row 0 x row 1) -- the identity the two-row link storage of the
+    FP32 / BF16 formats relies on."""
+    U = wi.random_links((4, 4, 2, 4), 0.4, 315)
+    r2 = np.conj(np.cross(U[..., 0, :], U[..., 1, :]))
+    assert np.max(np.abs(r2 - U[..., 2, :])) < 1e-13
+    assert np.max(np.abs(np.linalg.det(U) - 1.0)) < 1e-13
