@@ -18,7 +18,10 @@ d = 2 + 2 mu (-mu).  No bias and no nonlinearity: M_theta is linear, so the
 block BiCGGR iteration stays valid with it as M.
 
 Training minimises the mean over columns of ||M r - e||^2 / ||e||^2 for
-pairs with A e = r.  ``grad`` returns the real gradient packed as a complex
+pairs with A e = r (the error of the proposed correction), or of
+||r - A M r||^2 / ||r||^2 (the residual the correction leaves, which is what a
+preconditioner is for: it weights every eigenmode of A by its size in r
+instead of by 1/lambda).  ``grad`` returns the real gradient packed as a complex
 number, dl/d(Re W) + i dl/d(Im W) = 2 dl/d(conj W).  The adjoint layer is the
 same layer with W_0 -> W_0^dag and W_{+-mu} -> W_{-+mu}^dag, because the
 shift-with-link S_{+mu} has adjoint S_{-mu}.
@@ -130,6 +133,46 @@ def grad(op, theta, R: np.ndarray, E: np.ndarray):
     return lval, G
 
 
+def _gamma5(f: np.ndarray) -> np.ndarray:
+    """gamma5 = diag(1, 1, -1, -1) on the spin index of an oracle field (chiral basis)."""
+    out = f.copy()
+    out[..., 2:, :, :] *= -1.0
+    return out
+
+
+def loss_residual(op, theta, R: np.ndarray) -> float:
+    """Mean over columns of ||r - A M r||^2 / ||r||^2: the residual left after the correction M r
+    that the preconditioner proposes for a residual r (for a pair with A e = r this is
+    ||A (M r - e)||^2 / ||r||^2, the error measured in the residual norm)."""
+    y = forward(op, theta, R)
+    res = op.apply_A(y) - R
+    axes = tuple(range(R.ndim - 1))
+    return float(np.mean(np.sum(np.abs(res) ** 2, axis=axes) / np.sum(np.abs(R) ** 2, axis=axes)))
+
+
+def grad_residual(op, theta, R: np.ndarray):
+    """(loss_residual, gradient as dl/dRe + i dl/dIm).  dl/d(conj y) = A^H (A y - r) / ||r||^2 / P,
+    with A^H = gamma5 A gamma5 (gamma5-hermiticity of the operator); then the same backward pass
+    through the layers as ``grad``."""
+    zs = forward(op, theta, R, keep=True)
+    y = zs[-1]
+    axes = tuple(range(R.ndim - 1))
+    den = np.sum(np.abs(R) ** 2, axis=axes)
+    P = R.shape[-1]
+    res = op.apply_A(y) - R
+    lval = float(np.mean(np.sum(np.abs(res) ** 2, axis=axes) / den))
+    g = _gamma5(op.apply_A(_gamma5(res))) / den / P
+    G = np.zeros_like(theta)
+    for l in range(theta.shape[0] - 1, -1, -1):
+        z = zs[l]
+        for d in range(NDIR):
+            sz = shifted(op, z, d)
+            G[l, d] = 2.0 * np.einsum("nsal,ntal->st", g.reshape((-1,) + g.shape[-3:]),
+                                      np.conj(sz).reshape((-1,) + sz.shape[-3:]))
+        g = layer(op, adjoint_weights(theta[l]), g)
+    return lval, G
+
+
 def adam(theta, G, state, lr=1e-3, b1=0.9, b2=0.999, eps=1e-8):
     """One Adam step on the real and imaginary parts of theta (state: dict m, v, t)."""
     t = state.get("t", 0) + 1
@@ -144,8 +187,9 @@ def adam(theta, G, state, lr=1e-3, b1=0.9, b2=0.999, eps=1e-8):
     return theta - lr * step
 
 
-def train(op, theta, R: np.ndarray, E: np.ndarray, steps: int, L: int, lr: float = 1e-3):
-    """Adam for `steps` steps; batch b uses columns [b L, b L + L) (cycling).  Returns (theta, losses)."""
+def train(op, theta, R: np.ndarray, E: np.ndarray, steps: int, L: int, lr: float = 1e-3, residual: bool = False):
+    """Adam for `steps` steps; batch b uses columns [b L, b L + L) (cycling).  residual: train on
+    ``loss_residual`` (E unused) instead of ``loss``.  Returns (theta, losses)."""
     P = R.shape[-1]
     nb = max(1, P // L)
     state = {}
@@ -153,7 +197,7 @@ def train(op, theta, R: np.ndarray, E: np.ndarray, steps: int, L: int, lr: float
     for s in range(steps):
         b = s % nb
         sl = slice(b * L, b * L + L)
-        lv, G = grad(op, theta, R[..., sl], E[..., sl])
+        lv, G = grad_residual(op, theta, R[..., sl]) if residual else grad(op, theta, R[..., sl], E[..., sl])
         hist.append(lv)
         theta = adam(theta, G, state, lr)
     return theta, hist

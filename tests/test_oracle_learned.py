@@ -158,3 +158,40 @@ def test_adam_closed_form_steps():
     t2 = ln.adam(t1, -g, st, lr=lr)
     assert np.max(np.abs((t2 - t1) - lr / 19.0 * sign)) < 1e-9
     assert st["t"] == 2
+
+
+def test_residual_loss_gradient_matches_central_differences():
+    rng = np.random.default_rng(13)
+    op = _op(dims=(2, 2, 2, 2), bc_t=1)
+    th = _rand_theta(rng, 0.2)
+    R = op.from_block(wi.gaussian_block(op.V, 3, 15))
+    lv, G = ln.grad_residual(op, th, R)
+    assert abs(lv - ln.loss_residual(op, th, R)) < 1e-12
+    h = 1e-6
+    for _ in range(12):
+        idx = tuple(rng.integers(0, n) for n in th.shape)
+        for part in (1.0, 1j):
+            tp = th.copy()
+            tm = th.copy()
+            tp[idx] += h * part
+            tm[idx] -= h * part
+            fd = (ln.loss_residual(op, tp, R) - ln.loss_residual(op, tm, R)) / (2 * h)
+            an = G[idx].real if part == 1.0 else G[idx].imag
+            assert abs(fd - an) <= 1e-7 * max(1.0, abs(an))
+
+
+def test_residual_loss_closed_forms():
+    """Closed forms: M = 1 leaves the residual r - A r; and for exact pairs (A e = r) the residual
+    loss is the error of the correction measured through A, ||A (M r - e)||^2 / ||r||^2."""
+    op = _op(dims=(2, 4, 2, 2), kappa=0.1, csw=0.0, bc_t=0)
+    R = op.from_block(wi.gaussian_block(op.V, 2, 16))
+    axes = tuple(range(R.ndim - 1))
+    r2 = np.sum(np.abs(R) ** 2, axis=axes)
+    want = np.mean(np.sum(np.abs(R - op.apply_A(R)) ** 2, axis=axes) / r2)
+    assert abs(ln.loss_residual(op, ln.identity_theta(), R) - want) < 1e-14
+    E = op.from_block(wi.gaussian_block(op.V, 2, 17))
+    Rp = op.apply_A(E)
+    th = _rand_theta(np.random.default_rng(2), 0.1)
+    d = ln.forward(op, th, Rp) - E
+    want = np.mean(np.sum(np.abs(op.apply_A(d)) ** 2, axis=axes) / np.sum(np.abs(Rp) ** 2, axis=axes))
+    assert abs(ln.loss_residual(op, th, Rp) - want) < 1e-12 * max(1.0, want)
