@@ -110,10 +110,11 @@ typedef struct wd_solve_opts {
                               solver restarts from the FP64 true residual.  0: 1e-4 for FP32 and
                               1e-1 for BF16 storage of M (the learned M counts as FP32), no cycles
                               for FP64; < 0: no cycles */
-    int no_fallback;       /* 0: when a cycle of an inexact M stalls, diverges or breaks down, the
-                              solve starts again from X = 0 with the FP64 Jacobi preconditioner of
-                              the same j (M = I if j = 0); 1: the solve ends there with that
-                              status and X set to the cycle's best iterate */
+    int no_fallback;       /* 0: when a cycle of an inexact M, or a run with the learned M in any
+                              precision, stalls, diverges or breaks down, the solve starts again
+                              from X = 0 with the FP64 Jacobi preconditioner of the same j (M = I
+                              if j = 0); 1: the solve ends there with that status and X set to
+                              the cycle's best iterate or the run's recovery point */
     void* x_snap;          /* optional device buffer of snap_count block vectors of L columns:
                               the iterate X_k is copied into slot i after outer iteration
                               k = (i + 1) * snap_every (counted over all runs of the solve), for
@@ -316,14 +317,22 @@ int wd_learned_init(wd_ctx* ctx, int kind);
  * vectors of L columns and must not overlap. */
 int wd_learned_apply(wd_ctx* ctx, const void* R, void* Z, int L, int prec);
 
+/* Training losses: the error of the proposed correction, mean ||M_theta r - e||^2 / ||e||^2, or
+ * the residual it leaves, mean ||r - A M_theta r||^2 / ||r||^2 (e unused; needs wd_set_params). */
+#define WD_LOSS_ERROR 0
+#define WD_LOSS_RESIDUAL 1
+
 /* Train theta on pairs (r, e) with A e ~ r: minimise the mean over columns of
- * ||M_theta r - e||^2 / ||e||^2 with Adam (lr, beta1 0.9, beta2 0.999) for
+ * the loss of loss_kind (WD_LOSS_ERROR: ||M_theta r - e||^2 / ||e||^2,
+ * WD_LOSS_RESIDUAL: ||r - A M_theta r||^2 / ||r||^2, Ep may then be NULL)
+ * with Adam (lr, beta1 0.9, beta2 0.999) for
  * `steps` steps; batch b uses columns [b*L, b*L + L) of the n_pairs columns
  * of Rp and Ep (device block vectors of n_pairs columns each, FP64), cycling.
  * Starts from the current theta and leaves the trained theta set.  loss_hist
- * (host, may be NULL) receives one loss per step. */
+ * (host, may be NULL) receives one loss per step.  Every column of Ep must be
+ * non-zero and finite (WD_EINVAL otherwise, before any step). */
 int wd_learned_train(wd_ctx* ctx, const void* Rp, const void* Ep, int n_pairs, int L,
-                     int steps, double lr, float* loss_hist);
+                     int steps, double lr, int loss_kind, float* loss_hist);
 
 /* Training pairs generated by the solver itself: for each of the n snapshots
  * X_k in Xsnap (device, n block vectors of L columns, as written by
@@ -331,17 +340,19 @@ int wd_learned_train(wd_ctx* ctx, const void* Rp, const void* Ep, int n_pairs, i
  * the converged solution of A X = B.  Rp and Ep are device buffers of n * L
  * columns (the layout wd_learned_train takes); none of the buffers may
  * overlap.  A pair satisfies A e = r exactly (up to rounding): e is the
- * correction that the residual r asks for. */
+ * correction that the residual r asks for.  A snapshot taken at the solve's
+ * last iteration equals X and gives e = 0, which training rejects. */
 int wd_learned_pairs(wd_ctx* ctx, const void* B, const void* X, const void* Xsnap, int n, int L, void* Rp,
                      void* Ep);
 
 /* Copy the current theta to host memory (3*9*16 complex64). */
 int wd_get_learned(wd_ctx* ctx, float* theta_host);
 
-/* Loss (as in wd_learned_train) and its gradient with respect to theta on L
+/* Loss of loss_kind (as in wd_learned_train) and its gradient with respect to theta on L
  * pairs, without updating theta: G_host receives 3*9*16 complex128 holding
  * dl/dRe(theta) + i dl/dIm(theta).  For testing the backward kernels. */
-int wd_learned_grad(wd_ctx* ctx, const void* R, const void* E, int L, double* loss, double* G_host);
+int wd_learned_grad(wd_ctx* ctx, const void* R, const void* E, int L, int loss_kind, double* loss,
+                    double* G_host);
 
 /* ---------------------------------------------------------------------------
  * Utilities

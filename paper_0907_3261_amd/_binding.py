@@ -36,6 +36,8 @@ WD_F64, WD_F32, WD_BF16 = 0, 1, 2
 WD_F64_COEF_F32, WD_F64_COEF_BF16 = 3, 4   # Jacobi only: FP64 iterates, low-precision links and A_D^-1
 WD_PRECOND_NONE, WD_PRECOND_JACOBI, WD_PRECOND_LEARNED = 0, 1, 2
 WD_LEARNED_INIT_IDENTITY, WD_LEARNED_INIT_NEUMANN = 0, 1
+WD_LOSS_ERROR, WD_LOSS_RESIDUAL = 0, 1
+LOSS = {"error": WD_LOSS_ERROR, "residual": WD_LOSS_RESIDUAL}
 WD_JACOBI_BLOCK, WD_JACOBI_POINT = 0, 1
 WD_MAX_L = 16
 
@@ -90,8 +92,8 @@ SIGNATURES = [
     ("wd_learned_pairs", c_int, [c_void_p, c_void_p, c_void_p, c_void_p, c_int, c_int, c_void_p, c_void_p]),
     ("wd_get_learned", c_int, [c_void_p, c_void_p]),
     ("wd_learned_apply", c_int, [c_void_p, c_void_p, c_void_p, c_int, c_int]),
-    ("wd_learned_train", c_int, [c_void_p, c_void_p, c_void_p, c_int, c_int, c_int, c_double, c_void_p]),
-    ("wd_learned_grad", c_int, [c_void_p, c_void_p, c_void_p, c_int, c_void_p, c_void_p]),
+    ("wd_learned_train", c_int, [c_void_p, c_void_p, c_void_p, c_int, c_int, c_int, c_double, c_int, c_void_p]),
+    ("wd_learned_grad", c_int, [c_void_p, c_void_p, c_void_p, c_int, c_int, c_void_p, c_void_p]),
     ("wd_strerror", ctypes.c_char_p, [c_int]),
     ("wd_volume", c_longlong, [c_void_p]),
 ]
@@ -327,21 +329,24 @@ class Context:
                "wd_learned_apply")
         return Z
 
-    def learned_train(self, Rp, Ep, L: int, steps: int, lr: float = 1e-3):
-        """Train on pairs (Rp, Ep: device tensors of shape (P, 12, V)); returns the loss per step."""
+    def learned_train(self, Rp, Ep, L: int, steps: int, lr: float = 1e-3, loss: str = "error"):
+        """Train on pairs (Rp, Ep: device tensors of shape (P, 12, V); Ep may be None for the
+        residual loss); returns the loss per step."""
         P = Rp.shape[0]
         hist = np.zeros(max(steps, 1), dtype=np.float32)
-        _check(self._lib.wd_learned_train(self._h, self._block(Rp), self._block(Ep, P), P, int(L), int(steps),
-                                          float(lr), hist.ctypes.data), "wd_learned_train")
+        e = self._block(Ep, P) if Ep is not None else None
+        _check(self._lib.wd_learned_train(self._h, self._block(Rp), e, P, int(L), int(steps), float(lr), LOSS[loss],
+                                          hist.ctypes.data), "wd_learned_train")
         return hist[:steps]
 
-    def learned_grad(self, R, E):
+    def learned_grad(self, R, E, loss: str = "error"):
         L = R.shape[0]
-        loss = ctypes.c_double()
+        lv = ctypes.c_double()
         G = np.empty((3, 9, 4, 4), dtype=np.complex128)
-        _check(self._lib.wd_learned_grad(self._h, self._block(R), self._block(E, L), L, ctypes.byref(loss),
+        e = self._block(E, L) if E is not None else None
+        _check(self._lib.wd_learned_grad(self._h, self._block(R), e, L, LOSS[loss], ctypes.byref(lv),
                                          G.ctypes.data), "wd_learned_grad")
-        return loss.value, G
+        return lv.value, G
 
     # ---- block kernels
     def gram(self, P, Q):

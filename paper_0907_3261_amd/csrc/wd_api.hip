@@ -747,6 +747,16 @@ int solve_block(Driver& D, const double2* B, double2* X, int col0, int L, bool u
             if ((status == WD_DIVERGED || status == WD_STAGNATED) && res > saved && (r = S.copy(X, Xrec)))
                 return r;
             if (status != WD_NOT_CONVERGED) {
+                if (S.precond == WD_PRECOND_LEARNED && !D.op.no_fallback) {
+                    // a learned M that fails is replaced by the FP64 Jacobi preconditioner, from X = 0
+                    S.precond = D.fb_j > 0 ? WD_PRECOND_JACOBI : WD_PRECOND_NONE;
+                    S.j = D.fb_j;
+                    S.pin = Prec::F64;
+                    S.coef = 0;
+                    D.fell_back = true;
+                    use_x0 = false;
+                    continue;
+                }
                 if (L > 1 && !D.op.no_split) {
                     // Sec. 3.3: repeat the inversion with smaller L -- each half of the block
                     // is solved on its own from the current X (recursively)

@@ -317,6 +317,54 @@ __global__ void __launch_bounds__(kGB) k_loss(const float2* __restrict__ Y, cons
     }
 }
 
+// Residual-space loss: with Ay = A M r (FP64) and r, per element d = Ay - r; the loss partials
+// sum |d|^2 / ||r||^2 per column, and out = gamma5 d / (||r||^2 L), the input of the second
+// application of A in dl/d(conj y) = gamma5 A gamma5 d / (||r||^2 L) (gamma5 negates the lower
+// spin pair, planes k = 6..11 of a column).  out may be Ay.
+__global__ void __launch_bounds__(kGB) k_res_loss(const double2* Ay, const double2* __restrict__ R,
+                                                  const double* __restrict__ rn2, size_t n_per_col, int L,
+                                                  double2* out, double* __restrict__ partial) {
+    __shared__ double sh[kGB / 64];
+    const size_t n = n_per_col * L;
+    const size_t plane = n_per_col / 12;
+    double acc = 0.0;
+    for (size_t i = (size_t)blockIdx.x * kGB + threadIdx.x; i < n; i += (size_t)gridDim.x * kGB) {
+        const int col = (int)(i / n_per_col);
+        const int k = (int)((i - (size_t)col * n_per_col) / plane);
+        const double inv = 1.0 / rn2[col];
+        const double2 a = Ay[i], r = R[i];
+        const double dr = a.x - r.x, di = a.y - r.y;
+        acc += (dr * dr + di * di) * inv;
+        const double sc = (k >= 6 ? -inv : inv) / L;
+        out[i] = make_double2(dr * sc, di * sc);
+    }
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+#pragma unroll
+    for (int o = 32; o >= 1; o >>= 1) acc += __shfl_xor(acc, o, 64);
+    if (lane == 0) sh[w] = acc;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double sum = 0.0;
+        for (int q = 0; q < kGB / 64; ++q) sum += sh[q];
+        partial[blockIdx.x] = sum;
+    }
+}
+
+// FP32 activation -> FP64 block; gamma5 applied on request (the gradient's last factor)
+__global__ void k_to_f64(const float2* __restrict__ src, double2* __restrict__ dst, size_t n) {
+    const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) dst[i] = make_double2((double)src[i].x, (double)src[i].y);
+}
+__global__ void k_gamma5_to_f32(const double2* __restrict__ src, float2* __restrict__ dst, size_t n_per_col,
+                                size_t n) {
+    const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const size_t plane = n_per_col / 12;
+    const int k = (int)((i % n_per_col) / plane);
+    const double sg = k >= 6 ? -1.0 : 1.0;
+    dst[i] = make_float2((float)(sg * src[i].x), (float)(sg * src[i].y));
+}
+
 __global__ void __launch_bounds__(kGB) k_reduce_loss(const double* __restrict__ partial, int np, int L,
                                                      double* __restrict__ out) {
     __shared__ double sh[kGB];
@@ -466,6 +514,33 @@ hipError_t launch_learned(wd_ctx* c, const double2* R, double2* Z, int L, Prec p
     return e;
 }
 
+// Loss of one batch into w.loss and dl/d(conj y) (FP32) into w.g[0], from the forward output
+// w.z[2].  kind WD_LOSS_ERROR: ||y - e||^2 / ||e||^2; WD_LOSS_RESIDUAL: ||A y - r||^2 / ||r||^2,
+// whose gradient needs two FP64 applications of A (scratch: the solver blocks T1 and the Jacobi
+// temporary, ws[9] and ws[10], idle while training).
+hipError_t batch_loss(wd_ctx* c, LearnWs& w, const double2* Rb, const double2* Eb, int L, int kind, hipStream_t s) {
+    const size_t ncol = (size_t)12 * c->g.V, n = ncol * L;
+    const unsigned lblocks = 1024;
+    if (kind == WD_LOSS_ERROR) {
+        hipError_t e = launch_colnorms(Eb, ncol, L, c->partial, gram_blocks(ncol), w.en2, s);
+        if (e != hipSuccess) return e;
+        k_loss<<<lblocks, kGB, 0, s>>>(w.z[2], Eb, w.en2, ncol, L, w.g[0], w.lpart);
+        k_reduce_loss<<<1, kGB, 0, s>>>(w.lpart, lblocks, L, w.loss);
+        return hipGetLastError();
+    }
+    double2* t1 = c->ws[9];
+    double2* t2 = c->ws[10];
+    hipError_t e = launch_colnorms(Rb, ncol, L, c->partial, gram_blocks(ncol), w.en2, s);
+    if (e != hipSuccess) return e;
+    k_to_f64<<<nblk(n, 256), 256, 0, s>>>(w.z[2], t1, n);
+    if ((e = launch_apply_A(c, t1, t2, L, s)) != hipSuccess) return e;      // A y
+    k_res_loss<<<lblocks, kGB, 0, s>>>(t2, Rb, w.en2, ncol, L, t1, w.lpart);  // gamma5 (A y - r) / ...
+    k_reduce_loss<<<1, kGB, 0, s>>>(w.lpart, lblocks, L, w.loss);
+    if ((e = launch_apply_A(c, t1, t2, L, s)) != hipSuccess) return e;      // A gamma5 (A y - r)
+    k_gamma5_to_f32<<<nblk(n, 256), 256, 0, s>>>(t2, w.g[0], ncol, n);
+    return hipGetLastError();
+}
+
 int learned_ensure(wd_ctx* c) {
     LearnWs w;
     return learn_ws(c, w);
@@ -549,9 +624,13 @@ int wd_learned_apply(wd_ctx* c, const void* R, void* Z, int L, int prec) {
 }
 
 int wd_learned_train(wd_ctx* c, const void* Rp, const void* Ep, int n_pairs, int L, int steps, double lr,
-                     float* loss_hist) {
-    if (!c || !Rp || !Ep || L < 1 || L > c->max_L || n_pairs < L || steps < 0 || !(lr > 0.0)) return WD_EINVAL;
+                     int loss_kind, float* loss_hist) {
+    if (loss_kind != WD_LOSS_ERROR && loss_kind != WD_LOSS_RESIDUAL) return WD_EINVAL;
+    if (!c || !Rp || (!Ep && loss_kind == WD_LOSS_ERROR) || L < 1 || L > c->max_L || n_pairs < L || steps < 0 ||
+        !(lr > 0.0))
+        return WD_EINVAL;
     if (!c->have_links || !c->have_theta) return WD_ESTATE;
+    if (loss_kind == WD_LOSS_RESIDUAL && !c->have_params) return WD_ESTATE;
     LearnWs w;
     int r = learn_ws(c, w);
     if (r) return r;
@@ -559,22 +638,32 @@ int wd_learned_train(wd_ctx* c, const void* Rp, const void* Ep, int n_pairs, int
     const size_t V = c->g.V, ncol = 12 * V;
     const int nbatch = n_pairs / L;
     const int nparam = kNL * kND * 16;
+    // every normalising column (e, or r for the residual loss) must be non-zero and finite (a
+    // snapshot equal to the solution gives e = 0, which the normalised loss cannot take)
+    const void* Nv = loss_kind == WD_LOSS_ERROR ? Ep : Rp;
+    for (int b = 0; b < nbatch; ++b) {
+        double en2[WD_MAX_L];
+        if (launch_colnorms((const double2*)Nv + (size_t)b * L * ncol, ncol, L, c->partial, gram_blocks(ncol), w.en2,
+                            s) != hipSuccess ||
+            hipMemcpyAsync(en2, w.en2, sizeof(double) * L, hipMemcpyDeviceToHost, s) != hipSuccess ||
+            hipStreamSynchronize(s) != hipSuccess)
+            return WD_EHIP;
+        for (int i = 0; i < L; ++i)
+            if (!(en2[i] > 0.0) || !std::isfinite(en2[i])) return WD_EINVAL;
+    }
     if (launch_zero(w.m, nparam, s) != hipSuccess || launch_zero(w.v, nparam, s) != hipSuccess) return WD_EHIP;
     const unsigned lblocks = 1024;
     for (int step = 0; step < steps; ++step) {
         const int b = step % nbatch;
         const double2* Rb = (const double2*)Rp + (size_t)b * L * ncol;
-        const double2* Eb = (const double2*)Ep + (size_t)b * L * ncol;
-        // ||e||^2 per column
-        if (launch_colnorms(Eb, ncol, L, c->partial, gram_blocks(ncol), w.en2, s) != hipSuccess) return WD_EHIP;
+        const double2* Eb = Ep ? (const double2*)Ep + (size_t)b * L * ncol : nullptr;
         // forward: z0 = R (FP64) -> z1 -> z2 -> y (FP32, kept for the loss)
         if (launch_layer<StF64, StF32>(c, c->theta, Rb, w.z[0], L, s) != hipSuccess) return WD_EHIP;
         if (launch_layer<StF32, StF32>(c, c->theta + kND * 16, w.z[0], w.z[1], L, s) != hipSuccess) return WD_EHIP;
         if (launch_layer<StF32, StF32>(c, c->theta + 2 * kND * 16, w.z[1], w.z[2], L, s) != hipSuccess)
             return WD_EHIP;
         // loss and dl/d(conj y)
-        k_loss<<<lblocks, kGB, 0, s>>>(w.z[2], Eb, w.en2, ncol, L, w.g[0], w.lpart);
-        k_reduce_loss<<<1, kGB, 0, s>>>(w.lpart, lblocks, L, w.loss);
+        if (batch_loss(c, w, Rb, Eb, L, loss_kind, s) != hipSuccess) return WD_EHIP;
         // backward through layers 2, 1, 0
         int gi = 0;
         for (int l = kNL - 1; l >= 0; --l) {
@@ -608,9 +697,12 @@ int wd_learned_train(wd_ctx* c, const void* Rp, const void* Ep, int n_pairs, int
 
 // Loss and gradient of the current theta on L pairs, without updating theta
 // (G: host buffer of 3 * 9 * 16 complex128, dl/dRe + i dl/dIm).
-int wd_learned_grad(wd_ctx* c, const void* R, const void* E, int L, double* loss, double* G_host) {
-    if (!c || !R || !E || !loss || !G_host || L < 1 || L > c->max_L) return WD_EINVAL;
+int wd_learned_grad(wd_ctx* c, const void* R, const void* E, int L, int loss_kind, double* loss, double* G_host) {
+    if (loss_kind != WD_LOSS_ERROR && loss_kind != WD_LOSS_RESIDUAL) return WD_EINVAL;
+    if (!c || !R || (!E && loss_kind == WD_LOSS_ERROR) || !loss || !G_host || L < 1 || L > c->max_L)
+        return WD_EINVAL;
     if (!c->have_links || !c->have_theta) return WD_ESTATE;
+    if (loss_kind == WD_LOSS_RESIDUAL && !c->have_params) return WD_ESTATE;
     LearnWs w;
     int r = learn_ws(c, w);
     if (r) return r;
@@ -619,12 +711,10 @@ int wd_learned_grad(wd_ctx* c, const void* R, const void* E, int L, double* loss
     const unsigned lblocks = 1024;
     const double2* Rb = (const double2*)R;
     const double2* Eb = (const double2*)E;
-    if (launch_colnorms(Eb, ncol, L, c->partial, gram_blocks(ncol), w.en2, s) != hipSuccess) return WD_EHIP;
     if (launch_layer<StF64, StF32>(c, c->theta, Rb, w.z[0], L, s) != hipSuccess) return WD_EHIP;
     if (launch_layer<StF32, StF32>(c, c->theta + kND * 16, w.z[0], w.z[1], L, s) != hipSuccess) return WD_EHIP;
     if (launch_layer<StF32, StF32>(c, c->theta + 2 * kND * 16, w.z[1], w.z[2], L, s) != hipSuccess) return WD_EHIP;
-    k_loss<<<lblocks, kGB, 0, s>>>(w.z[2], Eb, w.en2, ncol, L, w.g[0], w.lpart);
-    k_reduce_loss<<<1, kGB, 0, s>>>(w.lpart, lblocks, L, w.loss);
+    if (batch_loss(c, w, Rb, Eb, L, loss_kind, s) != hipSuccess) return WD_EHIP;
     int gi = 0;
     for (int l = kNL - 1; l >= 0; --l) {
         for (int d = 0; d < kND; ++d) {
