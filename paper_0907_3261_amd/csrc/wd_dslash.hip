@@ -20,6 +20,8 @@
 //   JBLOCK Y = T^{-1} (Rh + kappa H X)             (Jacobi sweep, A_D = T)
 //   JPOINT Y = D^{-1} (Rh + kappa H X - (T - D) X) (Jacobi sweep, A_D = diag T)
 // The links arrive pre-multiplied by kappa.
+#include <type_traits>
+
 #include "wd_internal.h"
 
 namespace wd {
@@ -328,6 +330,171 @@ __global__ void __launch_bounds__(256)
     }
 }
 
+template <int D, int N, class F>
+__device__ __forceinline__ void static_for(F&& f) {
+    if constexpr (D < N) {
+        f(std::integral_constant<int, D>{});
+        static_for<D + 1, N>(f);
+    }
+}
+
+// Chiral 6x6 block chir of a clover-type field staged in LDS (planes chir*18 + i).
+__device__ __forceinline__ void herm_from_lds(Herm6<StF64>& T, const double2 (*sT)[64], int chir, int lane) {
+#pragma unroll
+    for (int i = 0; i < 3; ++i) {
+        const double2 p = sT[chir * 18 + i][lane];
+        T.d[2 * i] = p.x;
+        T.d[2 * i + 1] = p.y;
+    }
+#pragma unroll
+    for (int p = 0; p < 15; ++p) {
+        const double2 v = sT[chir * 18 + 3 + p][lane];
+        T.o[p] = {v.x, v.y};
+    }
+}
+
+// FP64 hop kernel for three or more columns, same modes and the same arithmetic
+// in the same order as k_hop (bit-identical results).  A workgroup owns a tile
+// of 64 sites.  Its four waves first stage in LDS the links of the tile's eight
+// hops (wave mu: U_mu(x) and U_mu(x - mu)) and the site's 6x6 blocks (T,
+// T^{-1} or the point form), 108 KB, read from HBM once per tile instead of
+// once per column tile.  Then wave w takes columns w, w + 4, ... one at a time
+// through all eight directions, with the next direction's neighbour spinor in
+// flight while the current one is applied.  Keeping one column per wave in
+// flight (instead of three) also keeps the neighbour reuse of a column within
+// the XCD's L2: at 32^3 x 64, L = 12 the sweep reads 25.2 instead of 29.0 GB
+// and the operator 20.5 instead of 25.8 GB.
+template <int MODE>
+__global__ void __launch_bounds__(256)
+    k_hop_f64(const Geom g, const SiteMap sm, const double2* __restrict__ Uk, const double2* __restrict__ Cl,
+              const double2* __restrict__ X, const double2* __restrict__ Rh, double2* __restrict__ Y, const int L) {
+    __shared__ double2 sU[72][64];
+    __shared__ double2 sT[36][64];
+    const int lane = threadIdx.x;
+    const int w = __builtin_amdgcn_readfirstlane(threadIdx.y);
+    const int s0 = map_site(g, sm, blockIdx.x, lane);
+    // the site depends on the block and the lane only, so all four waves agree on this exit
+    if (!__any(s0 >= 0)) return;
+    // a lane without a site (partial tile) takes the site of lane 0, which always has one: it
+    // repeats lane 0's arithmetic bit for bit and stores the same values to the same addresses,
+    // which keeps the stores unpredicated (a predicated store doubles the register use here)
+    const int s = s0 >= 0 ? s0 : map_site(g, sm, blockIdx.x, 0);
+    const size_t V = g.V;
+    const size_t cs = 12 * V;
+    const int x = s % g.lx, y = (s / g.lx) % g.ly, z = (s / g.sxy) % g.lz, t = s / g.sxyz;
+    constexpr uint32_t PB = 16;
+    uint32_t on[8];  // byte offsets of the neighbours x+, x-, y+, y-, z+, z-, t+, t-
+    on[0] = (uint32_t)((x == g.lx - 1) ? s - (g.lx - 1) : s + 1) * PB;
+    on[1] = (uint32_t)((x == 0) ? s + (g.lx - 1) : s - 1) * PB;
+    on[2] = (uint32_t)((y == g.ly - 1) ? s - (g.ly - 1) * g.lx : s + g.lx) * PB;
+    on[3] = (uint32_t)((y == 0) ? s + (g.ly - 1) * g.lx : s - g.lx) * PB;
+    on[4] = (uint32_t)((z == g.lz - 1) ? s - (g.lz - 1) * g.sxy : s + g.sxy) * PB;
+    on[5] = (uint32_t)((z == 0) ? s + (g.lz - 1) * g.sxy : s - g.sxy) * PB;
+    on[6] = (uint32_t)((t == g.lt - 1) ? s - (g.lt - 1) * g.sxyz : s + g.sxyz) * PB;
+    on[7] = (uint32_t)((t == 0) ? s + (g.lt - 1) * g.sxyz : s - g.sxyz) * PB;
+    const uint32_t o_s = (uint32_t)s * PB;
+    {
+        const uint32_t ob = (w == 0) ? on[1] : (w == 1) ? on[3] : (w == 2) ? on[5] : on[7];
+#pragma unroll
+        for (int k = 0; k < 9; ++k) {
+            const double2* pl = Uk + (size_t)(w * 9 + k) * V;
+            const cx<double> f = StF64::ldb(pl, o_s), b = StF64::ldb(pl, ob);
+            sU[(2 * w) * 9 + k][lane] = make_double2(f.re, f.im);
+            sU[(2 * w + 1) * 9 + k][lane] = make_double2(b.re, b.im);
+        }
+#pragma unroll
+        for (int j = 0; j < 9; ++j) {
+            const cx<double> v = StF64::ldb(Cl + (size_t)(w * 9 + j) * V, o_s);
+            sT[w * 9 + j][lane] = make_double2(v.re, v.im);
+        }
+    }
+    __syncthreads();
+    constexpr bool ADD = MODE != APPLY;
+    for (int c = w; c < L; c += 4) {
+        // the LDS lane index is made opaque per column, so that the compiler re-reads the staged
+        // links and blocks in every column instead of hoisting all 108 of them into registers
+        int ln = lane;
+        asm volatile("" : "+v"(ln));
+        const double2* xc = X + (size_t)c * cs;
+        cx<double> acc[12];
+        if (MODE == APPLY) {
+#pragma unroll
+            for (int chir = 0; chir < 2; ++chir) {
+                Herm6<StF64> T;
+                herm_from_lds(T, sT, chir, ln);
+                cx<double> v[6];
+#pragma unroll
+                for (int k = 0; k < 6; ++k) v[k] = StF64::ldb(xc + (size_t)(6 * chir + k) * V, o_s);
+#pragma unroll
+                for (int i = 0; i < 6; ++i) {
+                    cx<double> r = {0.0, 0.0};
+#pragma unroll
+                    for (int j = 0; j < 6; ++j) cfma(r, T.at(i, j), v[j]);
+                    acc[6 * chir + i] = r;
+                }
+            }
+        } else {
+            const double2* rc = Rh + (size_t)c * cs;
+#pragma unroll
+            for (int k = 0; k < 12; ++k) acc[k] = StF64::ldb_nt(rc + (size_t)k * V, o_s);
+        }
+        // time-direction neighbours are streamed, as in k_hop
+        cx<double> p[2][12];
+        auto load_dir = [&](cx<double>(&dst)[12], int d) {
+#pragma unroll
+            for (int k = 0; k < 12; ++k)
+                dst[k] = (d >= 6) ? StF64::ldb_nt(xc + (size_t)k * V, on[d]) : StF64::ldb(xc + (size_t)k * V, on[d]);
+        };
+        load_dir(p[0], 0);
+        static_for<0, 8>([&](auto dc) {
+            constexpr int D = decltype(dc)::value;
+            __builtin_amdgcn_sched_barrier(0);
+            if constexpr (D + 1 < 8) load_dir(p[(D + 1) % 2], D + 1);
+            cx<double> u[9];
+#pragma unroll
+            for (int k = 0; k < 9; ++k) {
+                const double2 v = sU[D * 9 + k][ln];
+                u[k] = {v.x, v.y};
+            }
+            hop_dir<double, D / 2, (D % 2) == 0, ADD>(acc, u, p[D % 2]);
+        });
+        __builtin_amdgcn_sched_barrier(0);
+        double2* yc = Y + (size_t)c * cs;
+        if (MODE == APPLY) {
+#pragma unroll
+            for (int k = 0; k < 12; ++k) StF64::stb_nt(yc + (size_t)k * V, o_s, acc[k]);
+        } else {
+#pragma unroll
+            for (int chir = 0; chir < 2; ++chir) {
+                Herm6<StF64> T;
+                herm_from_lds(T, sT, chir, ln);
+                cx<double> xs[6];
+                if (MODE == JPOINT) {
+#pragma unroll
+                    for (int k = 0; k < 6; ++k) xs[k] = StF64::ldb(xc + (size_t)(6 * chir + k) * V, o_s);
+                }
+#pragma unroll
+                for (int i = 0; i < 6; ++i) {
+                    cx<double> r;
+                    if (MODE == JBLOCK) {
+                        r = {0.0, 0.0};
+#pragma unroll
+                        for (int j = 0; j < 6; ++j) cfma(r, T.at(i, j), acc[6 * chir + j]);
+                    } else {
+                        // point reading: the diagonal slots hold 1/d
+                        cx<double> q = acc[6 * chir + i];
+#pragma unroll
+                        for (int j = 0; j < 6; ++j)
+                            if (j != i) q = q - T.at(i, j) * xs[j];
+                        r = T.d[i] * q;
+                    }
+                    StF64::stb_nt(yc + (size_t)(6 * chir + i) * V, o_s, r);
+                }
+            }
+        }
+    }
+}
+
 // First Jacobi sweep from G_0 = 0: Y = A_D^{-1} R (site-local, no hop).
 // SI: input storage, SF: compute (and clover) storage, SY: output storage,
 // SC: clover storage when it differs from SF (widened on load); with
@@ -442,6 +609,17 @@ hipError_t launch_hop_cols(const Geom& g, const LinkInfo& li, const void* Uk, co
 template <class SF, class SY, int MODE, class SC = SF>
 hipError_t launch_hop_t(const Geom& g, const LinkInfo& li, const void* Uk, const void* Cl, const void* X,
                         const void* Rh, void* Y, int L, hipStream_t s) {
+    if constexpr (std::is_same_v<SF, StF64> && std::is_same_v<SY, StF64> && std::is_same_v<SC, StF64>) {
+        // FP64 from three columns on: the LDS-staged kernel (measured faster at every L >= 3
+        // at 32^3 x 64; with one or two columns the staging cannot be shared by enough waves)
+        if (L >= 3) {
+            const SiteMap sm = make_site_map(g, 12.0 * L * 16 + 72.0 * 16);
+            dim3 block(64, 4), grid(sm.nblk);
+            k_hop_f64<MODE><<<grid, block, 0, s>>>(g, sm, (const double2*)Uk, (const double2*)Cl, (const double2*)X,
+                                                  (const double2*)Rh, (double2*)Y, L);
+            return hipGetLastError();
+        }
+    }
     const int CT = tile_cols(L, sizeof(typename SF::P) < 16);
     const int full = L / CT, rem = L % CT;
     hipError_t e = hipSuccess;

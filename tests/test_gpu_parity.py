@@ -155,14 +155,17 @@ def test_apply_rejects_bad_arguments(pkg):
 
 # ---------------------------------------------------------------- Jacobi
 
+@pytest.mark.parametrize("L", [2, 3, 7])
 @pytest.mark.parametrize("kind", [0, 1])
 @pytest.mark.parametrize("j", [0, 1, 2, 5, 12])
 @pytest.mark.parametrize("dims", [(4, 4, 6, 4), (8, 16, 8, 3)])
-def test_jacobi_matches_oracle(pkg, kind, j, dims):
+def test_jacobi_matches_oracle(pkg, kind, j, dims, L):
+    """Both A_D readings; L = 2 runs the register-tiled sweep, L = 3 and 7 the LDS-staged one (whose
+    four waves then take one, or two and one, columns each)."""
     U = wi.random_links(dims, 0.3, 109)
     op = WilsonClover(dims, U, 0.13, 1.6, bc_t=1, jacobi_kind="block" if kind == 0 else "point")
     c = _ctx(pkg, dims, U, 0.13, 1.6, 1, kind=kind)
-    R = wi.gaussian_block(op.V, 3, 110)
+    R = wi.gaussian_block(op.V, L, 110)
     Z = _host(c.jacobi(_dev(R), j))
     Zo = op.to_block(jacobi_apply(op, op.from_block(R), j))
     assert _maxrel(Z, Zo) < 1e-13
