@@ -472,11 +472,42 @@ def cpu_baseline(w, kappa):
     wall = time.perf_counter() - t0
     cpu = time.process_time() - c0
     gbs = reps * op.V * (1152 + 384 * L) / wall / 1e9
+    try:
+        from threadpoolctl import threadpool_info
+        blas = {i.get("internal_api", "?"): i.get("num_threads") for i in threadpool_info()}
+    except Exception:
+        blas = None
     return {"value": round(gbs, 4), "unit": "GB/s", "cores": max(1, round(cpu / wall)), "kind": "oracle",
             "sample": f"{reps} FP64 applications of A (numpy oracle) on a {dims[0]}x{dims[1]}x{dims[2]}x{dims[3]} "
                       f"slab of the same link ensemble, L={L}, {wall:.1f} s wall; algorithmic bytes per "
                       f"site as for the GPU operator kernel",
-            "host_cpus": len(os.sched_getaffinity(0))}
+            "host_cpus": len(os.sched_getaffinity(0)), "blas_threads": blas,
+            "per_config": cpu_per_config()}
+
+
+def cpu_per_config():
+    """Oracle time of one application of A at the configurations small enough for the host: the
+    4^4 dense-LU workload (L = 4), 8^3 x 16 (L = 12) and the paper's 16^3 x 32 at L = 1, 4 and 12
+    (one sample each; numpy's elementwise work runs on one core)."""
+    import numpy as np
+    import wdinputs as wi
+    from oracle import WilsonClover
+    out = {}
+    for name, Ls in (("lat4_L4_z4", (4,)), ("lat8x16_L12_point", (12,)), ("lat16x32_point", (1, 4, 12))):
+        w = wi.workload(name)
+        kappa = w.get("kappa_solve", w["kappa"])
+        kappa = kappa[0] if isinstance(kappa, tuple) else kappa
+        op = WilsonClover(w["dims"], wi.random_links(w["dims"], w["eps"], w["link_seed"]), kappa, w["csw"],
+                          bc_t=w["bc_t"])
+        for L in Ls:
+            X = op.from_block(wi.gaussian_block(op.V, L, 3))
+            t0 = time.perf_counter()
+            op.apply_A(X)
+            dt = time.perf_counter() - t0
+            out[f"{name} L={L}"] = {"s_per_apply": round(dt, 4),
+                                    "GBs": round(op.V * (1152 + 384 * L) / dt / 1e9, 4)}
+        print(f"[bench] cpu baseline {name}: {[out[f'{name} L={L}'] for L in Ls]}", file=sys.stderr, flush=True)
+    return out
 
 
 def main():

@@ -224,8 +224,8 @@ int jacobi_precond(wd_ctx* ctx, const void* R, void* Z, int L, int j, int prec);
  * may be NULL and is filled on every return after the arguments were
  * accepted.  Every column of B must be non-zero.  A run that breaks down,
  * diverges or stagnates is continued on the two halves of its block (see
- * no_split), following the advice of Sec. 3.3 to repeat the inversion with
- * smaller L.
+ * no_split): the remedy of Sec. 3.3 for a failed block run, solving again
+ * with fewer right-hand sides per block.
  * Returns WD_OK, a positive outcome code, or a negative error. */
 int bbicggr_solve(wd_ctx* ctx, const void* B, void* X, int L, double tol,
                   const wd_solve_opts* opts, wd_solve_info* info);

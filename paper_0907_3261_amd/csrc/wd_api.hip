@@ -758,7 +758,7 @@ int solve_block(Driver& D, const double2* B, double2* X, int col0, int L, bool u
                     continue;
                 }
                 if (L > 1 && !D.op.no_split) {
-                    // Sec. 3.3: repeat the inversion with smaller L -- each half of the block
+                    // Sec. 3.3's remedy, a block with fewer columns: each half of the block
                     // is solved on its own from the current X (recursively)
                     ++D.splits;
                     const int La = (L + 1) / 2;
