@@ -9,6 +9,7 @@
 // dl/dRe W_d + i dl/dIm W_d = 2 sum_{x,c,i} g(x) (S_d z)(x)^dag, the loss
 // mean_i ||y_i - e_i||^2 / ||e_i||^2 with its gradient, and Adam.
 #include <cmath>
+#include <type_traits>
 #include <complex>
 #include <cstring>
 #include <vector>
@@ -399,6 +400,98 @@ __global__ void k_adam(float2* __restrict__ theta, const double2* __restrict__ G
     theta[i] = th;
 }
 
+template <int D, int N, class F>
+__device__ __forceinline__ void static_for(F&& f) {
+    if constexpr (D < N) {
+        f(std::integral_constant<int, D>{});
+        static_for<D + 1, N>(f);
+    }
+}
+
+// One layer over L >= 3 columns with the links of a 64-site tile staged in LDS, as in the FP64
+// hop kernel: wave mu first stores U_mu(x) and U_mu(x - mu) for the tile's sites, then wave w
+// takes columns w, w + 4, ... one at a time through the nine terms (self, then forward and
+// backward per mu, the order of k_layer, so the results are bit-identical), with the next
+// term's input spinor in flight while the current term is applied.  The links are read from
+// HBM once per tile instead of once per column.  A lane without a site takes lane 0's site
+// and stores lane 0's values (unpredicated stores).
+template <class SI, class SO, class SL>
+__global__ void __launch_bounds__(256) k_layer_lds(const Geom g, const SiteMap sm, const typename SL::P* __restrict__ U,
+                                                   const float2* __restrict__ W, const typename SI::P* __restrict__ Zin,
+                                                   typename SO::P* __restrict__ Zout, const int L) {
+    using R = typename SL::R;
+    using PL = typename SL::P;
+    __shared__ PL sU[72][64];
+    const int lane = threadIdx.x;
+    const int w = __builtin_amdgcn_readfirstlane(threadIdx.y);
+    const int s0 = map_site(g, sm, blockIdx.x, lane);
+    if (!__any(s0 >= 0)) return;  // the same for all four waves
+    const int s = s0 >= 0 ? s0 : map_site(g, sm, blockIdx.x, 0);
+    const size_t V = g.V;
+    const int co[4] = {s % g.lx, (s / g.lx) % g.ly, (s / g.sxy) % g.lz, s / g.sxyz};
+    const int ext[4] = {g.lx, g.ly, g.lz, g.lt};
+    const int str[4] = {1, g.lx, g.sxy, g.sxyz};
+    int nb[9];  // input site of each term: self, then x+ x- y+ y- z+ z- t+ t-
+    nb[0] = s;
+#pragma unroll
+    for (int mu = 0; mu < 4; ++mu) {
+        nb[1 + 2 * mu] = (co[mu] + 1 == ext[mu]) ? s - (ext[mu] - 1) * str[mu] : s + str[mu];
+        nb[2 + 2 * mu] = (co[mu] == 0) ? s + (ext[mu] - 1) * str[mu] : s - str[mu];
+    }
+    {
+        const int bw = (w == 0) ? nb[2] : (w == 1) ? nb[4] : (w == 2) ? nb[6] : nb[8];
+#pragma unroll
+        for (int k = 0; k < 9; ++k) {
+            sU[(2 * w) * 9 + k][lane] = U[(size_t)(w * 9 + k) * V + s];
+            sU[(2 * w + 1) * 9 + k][lane] = U[(size_t)(w * 9 + k) * V + bw];
+        }
+    }
+    __syncthreads();
+    for (int c = w; c < L; c += 4) {
+        // the LDS lane index is opaque per column so that the staged links are read where they
+        // are used instead of all being hoisted into registers
+        int ln = lane;
+        asm volatile("" : "+v"(ln));
+        const typename SI::P* zc = Zin + (size_t)c * 12 * V;
+        cx<R> acc[1][12];
+#pragma unroll
+        for (int k = 0; k < 12; ++k) acc[0][k] = {R(0), R(0)};
+        Term<R, 1> t[2];
+        auto load_in = [&](Term<R, 1>& dst, int site) {
+#pragma unroll
+            for (int k = 0; k < 12; ++k) {
+                const auto v = SI::ld(zc, (size_t)k * V + site);
+                dst.p[0][k] = {(R)v.re, (R)v.im};
+            }
+        };
+        load_in(t[0], nb[0]);
+        static_for<0, 9>([&](auto dc) {
+            constexpr int D = decltype(dc)::value;
+            __builtin_amdgcn_sched_barrier(0);
+            if constexpr (D + 1 < 9) load_in(t[(D + 1) % 2], nb[D + 1]);
+            Term<R, 1>& cur = t[D % 2];
+            if constexpr (D == 0) {
+                term_apply<0>(cur, W, acc);
+            } else {
+                constexpr int mu = (D - 1) / 2;
+                constexpr bool fwd = (D % 2) == 1;
+                constexpr int plane0 = (fwd ? 2 * mu : 2 * mu + 1) * 9;
+#pragma unroll
+                for (int k = 0; k < 9; ++k) {
+                    const PL v = sU[plane0 + k][ln];
+                    cur.u[k] = {(R)v.x, (R)v.y};
+                }
+                term_apply<fwd ? 1 : 2>(cur, W + D * 16, acc);
+            }
+        });
+        __builtin_amdgcn_sched_barrier(0);
+        typename SO::P* oc = Zout + (size_t)c * 12 * V;
+#pragma unroll
+        for (int k = 0; k < 12; ++k)
+            SO::st(oc, (size_t)k * V + s, cx<typename SO::R>{(typename SO::R)acc[0][k].re, (typename SO::R)acc[0][k].im});
+    }
+}
+
 inline unsigned nblk(size_t n, unsigned b) { return (unsigned)((n + b - 1) / b); }
 
 template <class SI, class SO, class SL, int CT>
@@ -422,6 +515,16 @@ constexpr int kLayerCT = 1;
 template <class SI, class SO, class SL>
 hipError_t launch_layer(const wd_ctx* c, const typename SL::P* U, const float2* W, const void* in, void* out, int L,
                         hipStream_t s) {
+    if (std::is_same_v<SL, StF64> && L >= 3) {
+        // FP64: LDS-staged links from three columns on (one workgroup per tile, all columns;
+        // measured 12.8 against 15.2 ms per application of M at 32^3 x 64, L = 12; in FP32 the
+        // register-tiled kernel with its next-term prefetch stays 3 % faster)
+        const SiteMap sm = make_site_map(c->g, 12.0 * L * sizeof(typename SI::P) + 72.0 * sizeof(typename SL::P));
+        dim3 block(64, 4), grid(sm.nblk);
+        k_layer_lds<SI, SO, SL><<<grid, block, 0, s>>>(c->g, sm, U, W, (const typename SI::P*)in,
+                                                       (typename SO::P*)out, L);
+        return hipGetLastError();
+    }
     return launch_layer_ct<SI, SO, SL, kLayerCT>(c, U, W, in, out, 0, L / kLayerCT, s);
 }
 
