@@ -99,8 +99,9 @@ def traffic_from_profiles(mode: int):
         if d.get("src_hash") != src_hash():
             return None
         for k, v in d.get("bytes_per_launch", {}).items():
-            # the LDS-staged FP64 kernel (three or more columns): its one template argument is the mode
-            if k.startswith(f"void k_hop_f64<{mode}>"):
+            # the LDS-staged FP64 kernel (three or more columns): mode, iterate format (the timed
+            # sweep is the middle one, time-diagonal in and out: 3)
+            if k.startswith(f"void k_hop_f64<{mode}, {3 if mode == 1 else 0}>"):
                 return v
         for k, v in d.get("bytes_per_launch", {}).items():
             # template arguments of the register-tiled hop kernel: storage in, storage out, columns,
@@ -612,7 +613,7 @@ def main():
     copy_gbs = time_copy(torch, V, L)
     roof = {"bound": "hbm", "achieved": round(ach, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": round(ach / HBM_PEAK_GBS, 4), "traffic": traffic_from_profiles(1),
-            "kernel": (f"k_hop_f64<JBLOCK> (Jacobi sweep, L={L})" if L >= 3 else f"k_hop<StF64,StF64,CT,JBLOCK> (Jacobi sweep, L={L})"),
+            "kernel": (f"k_hop_f64<JBLOCK, time-diagonal in and out> (middle Jacobi sweep, L={L})" if L >= 3 else f"k_hop<StF64,StF64,CT,JBLOCK> (Jacobi sweep, L={L})"),
             "copy_GBs": round(copy_gbs, 1), "frac_of_copy": round(ach / copy_gbs, 4),
             "avg_launch_ms": round(ms_sweep, 4), "alg_bytes_per_launch": b_sweep}
     ach_a = b_apply / (ms_apply / 1e3) / 1e9

@@ -63,29 +63,13 @@ struct Herm6 {
     }
 };
 
-// acc (+/-)= projected-and-multiplied hop contribution of direction MU.
-// FWD: link U applied to (u - B d); BWD: U^dag applied to (u + B d).
+// acc (+/-)= link-multiplied hop contribution of direction MU from the projected
+// two-spinor h (h0: first spin component, h1: second; 3 colours each), whose
+// lower spin pair is rebuilt after the colour multiply.
+// FWD: link U applied to h = u - B d; BWD: U^dag applied to h = u + B d.
 template <typename R, int MU, bool FWD, bool ADD>
-__device__ __forceinline__ void hop_dir(cx<R> (&acc)[12], const cx<R> (&u)[9], const cx<R> (&p)[12]) {
-    // p is the neighbour spinor, index 3*spin + colour
-    cx<R> h0[3], h1[3];
-#pragma unroll
-    for (int c = 0; c < 3; ++c) {
-        const cx<R> s0 = p[c], s1 = p[3 + c], s2 = p[6 + c], s3 = p[9 + c];
-        if (MU == 0) {
-            h0[c] = FWD ? s0 + ti(s3) : s0 - ti(s3);
-            h1[c] = FWD ? s1 + ti(s2) : s1 - ti(s2);
-        } else if (MU == 1) {
-            h0[c] = FWD ? s0 + s3 : s0 - s3;
-            h1[c] = FWD ? s1 - s2 : s1 + s2;
-        } else if (MU == 2) {
-            h0[c] = FWD ? s0 + ti(s2) : s0 - ti(s2);
-            h1[c] = FWD ? s1 - ti(s3) : s1 + ti(s3);
-        } else {
-            h0[c] = FWD ? s0 - s2 : s0 + s2;
-            h1[c] = FWD ? s1 - s3 : s1 + s3;
-        }
-    }
+__device__ __forceinline__ void hop_mul_acc(cx<R> (&acc)[12], const cx<R> (&u)[9], const cx<R> (&h0)[3],
+                                            const cx<R> (&h1)[3]) {
     // colour: g = U h (forward) or U^dag h (backward)
     cx<R> g0[3], g1[3];
 #pragma unroll
@@ -133,6 +117,37 @@ __device__ __forceinline__ void hop_dir(cx<R> (&acc)[12], const cx<R> (&u)[9], c
             acc[9 + a] = acc[9 + a] - l3;
         }
     }
+}
+
+// The projected two-spinor of direction MU from a full neighbour spinor p
+// (index 3*spin + colour).
+template <typename R, int MU, bool FWD>
+__device__ __forceinline__ void project(const cx<R> (&p)[12], cx<R> (&h0)[3], cx<R> (&h1)[3]) {
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+        const cx<R> s0 = p[c], s1 = p[3 + c], s2 = p[6 + c], s3 = p[9 + c];
+        if (MU == 0) {
+            h0[c] = FWD ? s0 + ti(s3) : s0 - ti(s3);
+            h1[c] = FWD ? s1 + ti(s2) : s1 - ti(s2);
+        } else if (MU == 1) {
+            h0[c] = FWD ? s0 + s3 : s0 - s3;
+            h1[c] = FWD ? s1 - s2 : s1 + s2;
+        } else if (MU == 2) {
+            h0[c] = FWD ? s0 + ti(s2) : s0 - ti(s2);
+            h1[c] = FWD ? s1 - ti(s3) : s1 + ti(s3);
+        } else {
+            h0[c] = FWD ? s0 - s2 : s0 + s2;
+            h1[c] = FWD ? s1 - s3 : s1 + s3;
+        }
+    }
+}
+
+// acc (+/-)= projected-and-multiplied hop contribution of direction MU.
+template <typename R, int MU, bool FWD, bool ADD>
+__device__ __forceinline__ void hop_dir(cx<R> (&acc)[12], const cx<R> (&u)[9], const cx<R> (&p)[12]) {
+    cx<R> h0[3], h1[3];
+    project<R, MU, FWD>(p, h0, h1);
+    hop_mul_acc<R, MU, FWD, ADD>(acc, u, h0, h1);
 }
 
 // Links stored in FP32 or BF16 keep only their first two rows (12 reals,
@@ -353,21 +368,35 @@ __device__ __forceinline__ void herm_from_lds(Herm6<StF64>& T, const double2 (*s
     }
 }
 
-// FP64 hop kernel for three or more columns, same modes and the same arithmetic
-// in the same order as k_hop (bit-identical results).  A workgroup owns a tile
-// of 64 sites.  Its four waves first stage in LDS the links of the tile's eight
-// hops (wave mu: U_mu(x) and U_mu(x - mu)) and the site's 6x6 blocks (T,
-// T^{-1} or the point form), 108 KB, read from HBM once per tile instead of
-// once per column tile.  Then wave w takes columns w, w + 4, ... one at a time
-// through all eight directions, with the next direction's neighbour spinor in
-// flight while the current one is applied.  Keeping one column per wave in
-// flight (instead of three) also keeps the neighbour reuse of a column within
-// the XCD's L2: at 32^3 x 64, L = 12 the sweep reads 25.2 instead of 29.0 GB
-// and the operator 20.5 instead of 25.8 GB.
-template <int MODE>
+// Jacobi iterates between sweeps (FP64, three or more columns) are stored in
+// time-diagonal form: planes k < 6 hold a = u + d and planes k >= 6 hold
+// b = u - d, where u and d are the upper and lower spin pairs (k = 3*spin +
+// colour).  In the chiral basis gamma_t = [[0, 1], [1, 0]], so the forward
+// time hop needs only h = u - d = b of its neighbour and the backward one
+// only h = u + d = a: each time-direction neighbour load reads six planes
+// instead of twelve.  The other directions rebuild u = (a + b) / 2 and
+// d = (a - b) / 2 (a rounding of the last bit, well inside the FP64
+// tolerance).  The right-hand side and the final output of M stay in the
+// standard form.
+enum { FMT_IN_TD = 1, FMT_OUT_TD = 2 };
+
+// FP64 hop kernel for three or more columns, same modes as k_hop.  A
+// workgroup owns a tile of 64 sites.  Its four waves first stage in LDS the
+// links of the tile's eight hops (wave mu: U_mu(x) and U_mu(x - mu)) and the
+// site's 6x6 blocks (T, T^{-1} or the point form), 108 KB, read from HBM once
+// per tile instead of once per column tile.  Then wave w takes columns w,
+// w + 4, ... one at a time through all eight directions, with the next
+// direction's neighbour spinor in flight while the current one is applied.
+// Keeping one column per wave in flight (instead of three) also keeps the
+// neighbour reuse of a column within the XCD's L2.  FMT: time-diagonal input
+// and / or output (sweeps only); with FMT = 0 the arithmetic and its order
+// are k_hop's (bit-identical results).
+template <int MODE, int FMT = 0>
 __global__ void __launch_bounds__(256)
     k_hop_f64(const Geom g, const SiteMap sm, const double2* __restrict__ Uk, const double2* __restrict__ Cl,
               const double2* __restrict__ X, const double2* __restrict__ Rh, double2* __restrict__ Y, const int L) {
+    static_assert(MODE != APPLY || FMT == 0, "the operator takes and returns the standard form");
+    constexpr bool TD_IN = (FMT & FMT_IN_TD) != 0, TD_OUT = (FMT & FMT_OUT_TD) != 0;
     __shared__ double2 sU[72][64];
     __shared__ double2 sT[36][64];
     const int lane = threadIdx.x;
@@ -440,9 +469,16 @@ __global__ void __launch_bounds__(256)
 #pragma unroll
             for (int k = 0; k < 12; ++k) acc[k] = StF64::ldb_nt(rc + (size_t)k * V, o_s);
         }
-        // time-direction neighbours are streamed, as in k_hop
+        // neighbour spinor of direction d (time-direction neighbours are streamed, as in k_hop);
+        // in the time-diagonal form the time hops load only the half they project onto
         cx<double> p[2][12];
         auto load_dir = [&](cx<double>(&dst)[12], int d) {
+            if (TD_IN && d >= 6) {
+                const int k0 = (d == 6) ? 6 : 0;  // t+: b = u - d, t-: a = u + d
+#pragma unroll
+                for (int k = 0; k < 6; ++k) dst[k] = StF64::ldb_nt(xc + (size_t)(k0 + k) * V, on[d]);
+                return;
+            }
 #pragma unroll
             for (int k = 0; k < 12; ++k)
                 dst[k] = (d >= 6) ? StF64::ldb_nt(xc + (size_t)k * V, on[d]) : StF64::ldb(xc + (size_t)k * V, on[d]);
@@ -458,7 +494,22 @@ __global__ void __launch_bounds__(256)
                 const double2 v = sU[D * 9 + k][ln];
                 u[k] = {v.x, v.y};
             }
-            hop_dir<double, D / 2, (D % 2) == 0, ADD>(acc, u, p[D % 2]);
+            cx<double>(&q)[12] = p[D % 2];
+            if constexpr (TD_IN && D >= 6) {
+                // the loaded half is the projected two-spinor itself
+                cx<double> h0[3] = {q[0], q[1], q[2]}, h1[3] = {q[3], q[4], q[5]};
+                hop_mul_acc<double, 3, D == 6, ADD>(acc, u, h0, h1);
+            } else {
+                if constexpr (TD_IN) {
+#pragma unroll
+                    for (int k = 0; k < 6; ++k) {
+                        const cx<double> av = q[k], bv = q[k + 6];
+                        q[k] = 0.5 * (av + bv);
+                        q[k + 6] = 0.5 * (av - bv);
+                    }
+                }
+                hop_dir<double, D / 2, (D % 2) == 0, ADD>(acc, u, q);
+            }
         });
         __builtin_amdgcn_sched_barrier(0);
         double2* yc = Y + (size_t)c * cs;
@@ -466,14 +517,25 @@ __global__ void __launch_bounds__(256)
 #pragma unroll
             for (int k = 0; k < 12; ++k) StF64::stb_nt(yc + (size_t)k * V, o_s, acc[k]);
         } else {
+            cx<double> out[12];
 #pragma unroll
             for (int chir = 0; chir < 2; ++chir) {
                 Herm6<StF64> T;
                 herm_from_lds(T, sT, chir, ln);
                 cx<double> xs[6];
                 if (MODE == JPOINT) {
+                    if constexpr (TD_IN) {
+                        // own site, back to the standard form: u = (a + b) / 2, d = (a - b) / 2
 #pragma unroll
-                    for (int k = 0; k < 6; ++k) xs[k] = StF64::ldb(xc + (size_t)(6 * chir + k) * V, o_s);
+                        for (int k = 0; k < 6; ++k) {
+                            const cx<double> av = StF64::ldb(xc + (size_t)k * V, o_s);
+                            const cx<double> bv = StF64::ldb(xc + (size_t)(k + 6) * V, o_s);
+                            xs[k] = chir == 0 ? 0.5 * (av + bv) : 0.5 * (av - bv);
+                        }
+                    } else {
+#pragma unroll
+                        for (int k = 0; k < 6; ++k) xs[k] = StF64::ldb(xc + (size_t)(6 * chir + k) * V, o_s);
+                    }
                 }
 #pragma unroll
                 for (int i = 0; i < 6; ++i) {
@@ -490,7 +552,18 @@ __global__ void __launch_bounds__(256)
                             if (j != i) q = q - T.at(i, j) * xs[j];
                         r = T.d[i] * q;
                     }
-                    StF64::stb_nt(yc + (size_t)(6 * chir + i) * V, o_s, r);
+                    if constexpr (TD_OUT) {
+                        out[6 * chir + i] = r;
+                    } else {
+                        StF64::stb_nt(yc + (size_t)(6 * chir + i) * V, o_s, r);
+                    }
+                }
+            }
+            if constexpr (TD_OUT) {
+#pragma unroll
+                for (int k = 0; k < 6; ++k) {
+                    StF64::stb_nt(yc + (size_t)k * V, o_s, out[k] + out[k + 6]);
+                    StF64::stb_nt(yc + (size_t)(k + 6) * V, o_s, out[k] - out[k + 6]);
                 }
             }
         }
@@ -654,6 +727,21 @@ hipError_t launch_sweep(const wd_ctx* c, int pi, const void* X, const void* Rh, 
     return launch_hop_t<SF, SY, JBLOCK, SC>(c->g, link_info(c), c->f.Uk[pi], c->f.Ti[pi], X, Rh, Y, L, s);
 }
 
+// One FP64 sweep of three or more columns with the iterates in the format FMT
+// (FMT_IN_TD / FMT_OUT_TD: time-diagonal input / output).
+template <int FMT>
+hipError_t launch_sweep_td(const wd_ctx* c, const double2* X, const double2* R, double2* Y, int L, hipStream_t s) {
+    const SiteMap sm = make_site_map_rows(c->g, 12.0 * L * 16 + 72.0 * 16);
+    dim3 block(64, 4), grid(sm.nblk);
+    if (c->jacobi_kind == WD_JACOBI_POINT)
+        k_hop_f64<JPOINT, FMT><<<grid, block, 0, s>>>(c->g, sm, (const double2*)c->f.Uk[0],
+                                                      (const double2*)c->f.Tp[0], X, R, Y, L);
+    else
+        k_hop_f64<JBLOCK, FMT><<<grid, block, 0, s>>>(c->g, sm, (const double2*)c->f.Uk[0],
+                                                      (const double2*)c->f.Ti[0], X, R, Y, L);
+    return hipGetLastError();
+}
+
 // j sweeps with FP64 vectors and arithmetic and the links and A_D^{-1} of
 // storage format SC (FP32 or BF16): a fixed linear operator, unlike the
 // low-precision form, whose rounding of the vectors makes it nonlinear.
@@ -695,6 +783,9 @@ hipError_t launch_apply_A(const wd_ctx* c, const double2* X, double2* Y, int L, 
 }
 
 hipError_t launch_sweep_f64(const wd_ctx* c, const double2* X, const double2* R, double2* Y, int L, hipStream_t s) {
+    // the sweep jacobi_precond runs most often: from three columns on, the middle sweep with
+    // time-diagonal input and output
+    if (L >= 3) return launch_sweep_td<FMT_IN_TD | FMT_OUT_TD>(c, X, R, Y, L, s);
     return launch_sweep<StF64, StF64>(c, 0, X, R, Y, L, s);
 }
 
@@ -736,7 +827,18 @@ hipError_t launch_jacobi(wd_ctx* c, const double2* R, double2* Z, int L, int j, 
     for (int i = 2; i <= j; ++i) {
         double2* in = out;
         out = ((j - i) % 2 == 0) ? Z : tmp;
-        e = launch_sweep<StF64, StF64>(c, 0, in, R, out, L, s);
+        if (L >= 3 && j >= 3) {
+            // iterates between sweeps in the time-diagonal form: the second sweep reads the
+            // standard output of the first, the last one writes Z in the standard form
+            if (i == 2)
+                e = launch_sweep_td<FMT_OUT_TD>(c, in, R, out, L, s);
+            else if (i < j)
+                e = launch_sweep_td<FMT_IN_TD | FMT_OUT_TD>(c, in, R, out, L, s);
+            else
+                e = launch_sweep_td<FMT_IN_TD>(c, in, R, out, L, s);
+        } else {
+            e = launch_sweep<StF64, StF64>(c, 0, in, R, out, L, s);
+        }
         if (e != hipSuccess) return e;
     }
     return hipSuccess;
