@@ -570,6 +570,165 @@ __global__ void __launch_bounds__(256)
     }
 }
 
+// FP32 / BF16 hop kernel for three or more columns (used for FP32): the LDS-staged
+// structure of k_hop_f64 in the compute type (float).  The staging rebuilds the third row of
+// every two-row link once per tile (instead of once per column tile) and widens
+// the links and the 6x6 blocks to float, 54 KB of LDS; the arithmetic and its
+// order are k_hop's, so the results are bit-identical to it.
+template <class SF, class SY, int MODE>
+__global__ void __launch_bounds__(256)
+    k_hop_lds_lp(const Geom g, const SiteMap sm, const typename SF::P* __restrict__ Uk,
+                 const typename SF::P* __restrict__ Cl, const typename SF::P* __restrict__ X,
+                 const typename SF::P* __restrict__ Rh, typename SY::P* __restrict__ Y, const int L,
+                 const float invk, const int bc_t) {
+    using R = typename SF::R;
+    using PF = typename SF::P;
+    static_assert(sizeof(R) == 4, "FP32 compute");
+    __shared__ float2 sU[72][64];
+    __shared__ float2 sT[36][64];
+    const int lane = threadIdx.x;
+    const int w = __builtin_amdgcn_readfirstlane(threadIdx.y);
+    const int s0 = map_site(g, sm, blockIdx.x, lane);
+    if (!__any(s0 >= 0)) return;  // the same for all four waves
+    // a lane without a site takes lane 0's site (unpredicated stores, as in k_hop_f64)
+    const int s = s0 >= 0 ? s0 : map_site(g, sm, blockIdx.x, 0);
+    const size_t V = g.V;
+    const size_t cs = 12 * V;
+    const int x = s % g.lx, y = (s / g.lx) % g.ly, z = (s / g.sxy) % g.lz, t = s / g.sxyz;
+    constexpr uint32_t PB = sizeof(PF);
+    uint32_t on[8];
+    on[0] = (uint32_t)((x == g.lx - 1) ? s - (g.lx - 1) : s + 1) * PB;
+    on[1] = (uint32_t)((x == 0) ? s + (g.lx - 1) : s - 1) * PB;
+    on[2] = (uint32_t)((y == g.ly - 1) ? s - (g.ly - 1) * g.lx : s + g.lx) * PB;
+    on[3] = (uint32_t)((y == 0) ? s + (g.ly - 1) * g.lx : s - g.lx) * PB;
+    on[4] = (uint32_t)((z == g.lz - 1) ? s - (g.lz - 1) * g.sxy : s + g.sxy) * PB;
+    on[5] = (uint32_t)((z == 0) ? s + (g.lz - 1) * g.sxy : s - g.sxy) * PB;
+    on[6] = (uint32_t)((t == g.lt - 1) ? s - (g.lt - 1) * g.sxyz : s + g.sxyz) * PB;
+    on[7] = (uint32_t)((t == 0) ? s + (g.lt - 1) * g.sxyz : s - g.sxyz) * PB;
+    const uint32_t o_s = (uint32_t)s * PB;
+    {
+        // wave mu: the two stored rows of U_mu(x) and U_mu(x - mu), completed by third_row (the
+        // antiperiodic sign of the time links on the last slice, seen from t = Lt - 1 forward and
+        // from t = 0 backward), then stored in LDS as full 3 x 3 float matrices
+        const uint32_t ob = (w == 0) ? on[1] : (w == 1) ? on[3] : (w == 2) ? on[5] : on[7];
+        const bool neg_f = (w == 3) && bc_t && t == g.lt - 1, neg_b = (w == 3) && bc_t && t == 0;
+        cx<R> uf[9], ub[9];
+#pragma unroll
+        for (int k = 0; k < 6; ++k) {
+            const PF* pl = Uk + (size_t)(w * 6 + k) * V;
+            uf[k] = SF::ldb(pl, o_s);
+            ub[k] = SF::ldb(pl, ob);
+        }
+        third_row<R>(uf, invk, neg_f);
+        third_row<R>(ub, invk, neg_b);
+#pragma unroll
+        for (int k = 0; k < 9; ++k) {
+            sU[(2 * w) * 9 + k][lane] = make_float2(uf[k].re, uf[k].im);
+            sU[(2 * w + 1) * 9 + k][lane] = make_float2(ub[k].re, ub[k].im);
+        }
+#pragma unroll
+        for (int j = 0; j < 9; ++j) {
+            const cx<R> v = SF::ldb_nt(Cl + (size_t)(w * 9 + j) * V, o_s);
+            sT[w * 9 + j][lane] = make_float2(v.re, v.im);
+        }
+    }
+    __syncthreads();
+    constexpr bool ADD = MODE != APPLY;
+    for (int c = w; c < L; c += 4) {
+        int ln = lane;
+        asm volatile("" : "+v"(ln));
+        const PF* xc = X + (size_t)c * cs;
+        cx<R> acc[12];
+        auto herm = [&](Herm6<StF32>& T, int chir) {
+#pragma unroll
+            for (int i = 0; i < 3; ++i) {
+                const float2 q = sT[chir * 18 + i][ln];
+                T.d[2 * i] = q.x;
+                T.d[2 * i + 1] = q.y;
+            }
+#pragma unroll
+            for (int q = 0; q < 15; ++q) {
+                const float2 v = sT[chir * 18 + 3 + q][ln];
+                T.o[q] = {v.x, v.y};
+            }
+        };
+        if (MODE == APPLY) {
+#pragma unroll
+            for (int chir = 0; chir < 2; ++chir) {
+                Herm6<StF32> T;
+                herm(T, chir);
+                cx<R> v[6];
+#pragma unroll
+                for (int k = 0; k < 6; ++k) v[k] = SF::ldb(xc + (size_t)(6 * chir + k) * V, o_s);
+#pragma unroll
+                for (int i = 0; i < 6; ++i) {
+                    cx<R> r = {R(0), R(0)};
+#pragma unroll
+                    for (int j = 0; j < 6; ++j) cfma(r, T.at(i, j), v[j]);
+                    acc[6 * chir + i] = r;
+                }
+            }
+        } else {
+            const PF* rc = Rh + (size_t)c * cs;
+#pragma unroll
+            for (int k = 0; k < 12; ++k) acc[k] = SF::ldb_nt(rc + (size_t)k * V, o_s);
+        }
+        cx<R> p[2][12];
+        auto load_dir = [&](cx<R>(&dst)[12], int d) {
+#pragma unroll
+            for (int k = 0; k < 12; ++k)
+                dst[k] = (d >= 6) ? SF::ldb_nt(xc + (size_t)k * V, on[d]) : SF::ldb(xc + (size_t)k * V, on[d]);
+        };
+        load_dir(p[0], 0);
+        static_for<0, 8>([&](auto dc) {
+            constexpr int D = decltype(dc)::value;
+            __builtin_amdgcn_sched_barrier(0);
+            if constexpr (D + 1 < 8) load_dir(p[(D + 1) % 2], D + 1);
+            cx<R> u[9];
+#pragma unroll
+            for (int k = 0; k < 9; ++k) {
+                const float2 v = sU[D * 9 + k][ln];
+                u[k] = {v.x, v.y};
+            }
+            hop_dir<R, D / 2, (D % 2) == 0, ADD>(acc, u, p[D % 2]);
+        });
+        __builtin_amdgcn_sched_barrier(0);
+        typename SY::P* yc = Y + (size_t)c * cs;
+        const uint32_t o_y = (uint32_t)s * (uint32_t)sizeof(typename SY::P);
+        if (MODE == APPLY) {
+#pragma unroll
+            for (int k = 0; k < 12; ++k) store_out<SY>(yc + (size_t)k * V, o_y, acc[k]);
+        } else {
+#pragma unroll
+            for (int chir = 0; chir < 2; ++chir) {
+                Herm6<StF32> T;
+                herm(T, chir);
+                cx<R> xs[6];
+                if (MODE == JPOINT) {
+#pragma unroll
+                    for (int k = 0; k < 6; ++k) xs[k] = SF::ldb(xc + (size_t)(6 * chir + k) * V, o_s);
+                }
+#pragma unroll
+                for (int i = 0; i < 6; ++i) {
+                    cx<R> r;
+                    if (MODE == JBLOCK) {
+                        r = {R(0), R(0)};
+#pragma unroll
+                        for (int j = 0; j < 6; ++j) cfma(r, T.at(i, j), acc[6 * chir + j]);
+                    } else {
+                        cx<R> q = acc[6 * chir + i];
+#pragma unroll
+                        for (int j = 0; j < 6; ++j)
+                            if (j != i) q = q - T.at(i, j) * xs[j];
+                        r = T.d[i] * q;
+                    }
+                    store_out<SY>(yc + (size_t)(6 * chir + i) * V, o_y, r);
+                }
+            }
+        }
+    }
+}
+
 // First Jacobi sweep from G_0 = 0: Y = A_D^{-1} R (site-local, no hop).
 // SI: input storage, SF: compute (and clover) storage, SY: output storage,
 // SC: clover storage when it differs from SF (widened on load); with
@@ -692,6 +851,20 @@ hipError_t launch_hop_t(const Geom& g, const LinkInfo& li, const void* Uk, const
             dim3 block(64, 4), grid(sm.nblk);
             k_hop_f64<MODE><<<grid, block, 0, s>>>(g, sm, (const double2*)Uk, (const double2*)Cl, (const double2*)X,
                                                   (const double2*)Rh, (double2*)Y, L);
+            return hipGetLastError();
+        }
+    }
+    if constexpr (std::is_same_v<SF, StF32> && std::is_same_v<SC, SF>) {
+        // FP32 from three columns on: the LDS-staged kernel (sweep 2.51 against 2.96 ms at
+        // 32^3 x 64, L = 12; BF16 keeps the register-tiled kernel, whose four-column tiles share
+        // each rebuilt link: 1.42 against 1.52 ms LDS-staged)
+        if (L >= 3) {
+            const SiteMap sm = make_site_map_rows(g, 12.0 * L * sizeof(typename SF::P) + 72.0 * 8);
+            dim3 block(64, 4), grid(sm.nblk);
+            k_hop_lds_lp<SF, SY, MODE><<<grid, block, 0, s>>>(g, sm, (const typename SF::P*)Uk,
+                                                             (const typename SF::P*)Cl, (const typename SF::P*)X,
+                                                             (const typename SF::P*)Rh, (typename SY::P*)Y, L,
+                                                             (float)li.invk, li.bc_t);
             return hipGetLastError();
         }
     }
