@@ -575,6 +575,10 @@ def main():
         X.fill_(1.0)
         for _ in range(3):
             Y.copy_(X)
+        # one application of the learned M (Neumann start) in each precision, for its layer kernels
+        ctx.learned_init("neumann")
+        for prec in ("f64", "f32"):
+            ctx.learned_apply(X, Y, prec)
         torch.cuda.synchronize()
         print(json.dumps({"sweep_ms": ms_sweep, "apply_ms": ms_apply, "sweep_lowp_ms": ms_lowp,
                           "copy_bytes_read": X.numel() * 16,

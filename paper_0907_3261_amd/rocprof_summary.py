@@ -103,12 +103,19 @@ def main():
         for r in counters(db):
             table.setdefault(r["kernel"], {})[r["counter"]] = r["avg"]
     scale = {}
-    copy = [k for k in table if "copyBuffer" in k]
-    if a.copy_bytes and copy:
+    if a.copy_bytes:
+        # calibrate on the largest device copy of the run (the copy of copy_bytes; other, smaller
+        # copies of the same kernel would dilute an average)
         for ctr in ("FETCH_SIZE", "WRITE_SIZE"):
-            v = table[copy[0]].get(ctr)
-            if v:
-                scale[ctr] = a.copy_bytes / (v * 1024.0)
+            best = None
+            for db in a.db:
+                con = sqlite3.connect(db)
+                r = con.execute("select max(value) from counters_collection where counter_name = ? and "
+                                "kernel_name like '%copyBuffer%'", (ctr,)).fetchone()
+                if r and r[0]:
+                    best = r[0] if best is None else max(best, r[0])
+            if best:
+                scale[ctr] = a.copy_bytes / (best * 1024.0)
     print(f"copy calibration (bytes per reported KiB / 1024): {scale}")
     res = {}
     for k, d in table.items():
