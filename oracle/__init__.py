@@ -5,7 +5,8 @@ and its Python binding) imports, links or calls this package.  Only the
 tests, ``__graft_entry__.smoke()`` and the ``cpu_baseline`` leg of
 ``bench.py`` use it.
 
-It is plain numpy in float64/complex128, written for obvious correctness,
+It is plain numpy in float64/complex128 (float32 where ``lowp`` emulates a
+storage format), written for obvious correctness,
 not speed, and it shares no code, tables or constants with the HIP path.
 It works in its own array layout (fields shaped ``(Lt, Lz, Ly, Lx, 4, 3, L)``:
 t, z, y, x, spin, colour, column) and converts from/to the exchange layout
@@ -23,9 +24,14 @@ Contents (each function cites the passage it follows):
 * ``bicgstab`` -- preconditioned block BiCGSTAB (the published block
                  version of BiCGSTAB), the foil whose recursive residual drifts
                  from the true one, which BiCGGR is built to avoid (Sec. 1).
+* ``lowp``    -- the low-precision storage of the Jacobi preconditioner
+                 and operator: FP32 / BF16 (round-to-nearest-even) rounding of
+                 the links (two stored rows, the third rebuilt), the site
+                 matrices, inputs and stored iterates, with float32
+                 arithmetic.
 * ``learned`` -- the linear gauge-covariant network layers used as an
-                 alternative preconditioner: forward, adjoint, weight
-                 gradients.
+                 alternative preconditioner: forward, adjoint, the error and
+                 residual losses with their gradients, Adam.
 
 The operator itself is not printed in the paper (Sec. 2 defers it to the
 companion application paper); the convention used here is the standard
