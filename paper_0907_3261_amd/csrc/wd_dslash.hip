@@ -345,14 +345,6 @@ __global__ void __launch_bounds__(256)
     }
 }
 
-template <int D, int N, class F>
-__device__ __forceinline__ void static_for(F&& f) {
-    if constexpr (D < N) {
-        f(std::integral_constant<int, D>{});
-        static_for<D + 1, N>(f);
-    }
-}
-
 // Chiral 6x6 block chir of a clover-type field staged in LDS (planes chir*18 + i).
 __device__ __forceinline__ void herm_from_lds(Herm6<StF64>& T, const double2 (*sT)[64], int chir, int lane) {
 #pragma unroll

@@ -4,6 +4,7 @@
 #pragma once
 
 #include <hip/hip_runtime.h>
+#include <type_traits>
 #include <cstddef>
 #include <cstdint>
 
@@ -155,6 +156,16 @@ struct StBF16 {
     }
     WD_BYTE_OFFSET_ACCESSORS
 };
+
+// Compile-time loop: f(std::integral_constant<int, D>) for D = D0 .. N - 1, so
+// that the loop index can select template arguments (hop direction, term).
+template <int D, int N, class F>
+__device__ __forceinline__ void static_for(F&& f) {
+    if constexpr (D < N) {
+        f(std::integral_constant<int, D>{});
+        static_for<D + 1, N>(f);
+    }
+}
 
 // ---------------------------------------------------------------------------
 // Lattice geometry

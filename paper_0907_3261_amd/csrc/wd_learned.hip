@@ -400,14 +400,6 @@ __global__ void k_adam(float2* __restrict__ theta, const double2* __restrict__ G
     theta[i] = th;
 }
 
-template <int D, int N, class F>
-__device__ __forceinline__ void static_for(F&& f) {
-    if constexpr (D < N) {
-        f(std::integral_constant<int, D>{});
-        static_for<D + 1, N>(f);
-    }
-}
-
 // One layer over L >= 3 columns with the links of a 64-site tile staged in LDS, as in the FP64
 // hop kernel: wave mu first stores U_mu(x) and U_mu(x - mu) for the tile's sites, then wave w
 // takes columns w, w + 4, ... one at a time through the nine terms (self, then forward and
