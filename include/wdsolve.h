@@ -255,10 +255,11 @@ int bbicgstab_solve(wd_ctx* ctx, const void* B, void* X, int L, double tol,
  * low-precision kernel runs on them (mode 0 writes Y in FP64; mode 1 keeps
  * its low-precision output internal and leaves Y untouched).  Mode 1 also
  * takes WD_F64_COEF_F32 / WD_F64_COEF_BF16: the FP64 sweep with the links and
- * A_D^{-1} in that format, writing Y.  In FP64 with L >= 3, mode 1 runs the
- * middle sweep of jacobi_precond, which keeps the iterates in a time-diagonal
- * form: X and Y hold u + d in planes 0-5 and u - d in planes 6-11 (u, d: the
- * upper and lower spin pairs), R the standard form. */
+ * A_D^{-1} in that format, writing Y.  With FP64 vectors (WD_F64 and the two
+ * coefficient formats) and L >= 3, mode 1 runs the middle sweep of
+ * jacobi_precond, which keeps the iterates in a time-diagonal form: X and Y
+ * hold u + d in planes 0-5 and u - d in planes 6-11 (u, d: the upper and lower
+ * spin pairs), R the standard form. */
 int wd_hop_repeat(wd_ctx* ctx, const void* X, const void* R, void* Y, int L, int mode, int prec, int nrep);
 
 /* ---------------------------------------------------------------------------

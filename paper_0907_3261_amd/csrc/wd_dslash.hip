@@ -383,10 +383,11 @@ enum { FMT_IN_TD = 1, FMT_OUT_TD = 2 };
 // neighbour reuse of a column within the XCD's L2.  FMT: time-diagonal input
 // and / or output (sweeps only); with FMT = 0 the arithmetic and its order
 // are k_hop's (bit-identical results).
-template <int MODE, int FMT = 0>
+template <int MODE, int FMT = 0, class SC = StF64>
 __global__ void __launch_bounds__(256)
-    k_hop_f64(const Geom g, const SiteMap sm, const double2* __restrict__ Uk, const double2* __restrict__ Cl,
-              const double2* __restrict__ X, const double2* __restrict__ Rh, double2* __restrict__ Y, const int L) {
+    k_hop_f64(const Geom g, const SiteMap sm, const typename SC::P* __restrict__ Uk,
+              const typename SC::P* __restrict__ Cl, const double2* __restrict__ X, const double2* __restrict__ Rh,
+              double2* __restrict__ Y, const int L, const double invk = 0.0, const int bc_t = 0) {
     static_assert(MODE != APPLY || FMT == 0, "the operator takes and returns the standard form");
     constexpr bool TD_IN = (FMT & FMT_IN_TD) != 0, TD_OUT = (FMT & FMT_OUT_TD) != 0;
     __shared__ double2 sU[72][64];
@@ -415,20 +416,43 @@ __global__ void __launch_bounds__(256)
     on[7] = (uint32_t)((t == 0) ? s + (g.lt - 1) * g.sxyz : s - g.sxyz) * PB;
     const uint32_t o_s = (uint32_t)s * PB;
     {
+        // coefficient fields in storage SC: FP64, or FP32 / BF16 (two-row links, completed by
+        // third_row, and 6x6 blocks, all widened to FP64 here, once per tile)
+        constexpr uint32_t PC = sizeof(typename SC::P);
+        const auto co = [](uint32_t o) -> uint32_t { return (o / PB) * PC; };
         const uint32_t ob = (w == 0) ? on[1] : (w == 1) ? on[3] : (w == 2) ? on[5] : on[7];
+        if constexpr (kCompressedLinks<SC>) {
+            const bool neg_f = (w == 3) && bc_t && t == g.lt - 1, neg_b = (w == 3) && bc_t && t == 0;
+            cx<double> uf[9], ub[9];
 #pragma unroll
-        for (int k = 0; k < 9; ++k) {
-            const double2* pl = Uk + (size_t)(w * 9 + k) * V;
-            const cx<double> f = StF64::ldb(pl, o_s), b = StF64::ldb(pl, ob);
-            sU[(2 * w) * 9 + k][lane] = make_double2(f.re, f.im);
-            sU[(2 * w + 1) * 9 + k][lane] = make_double2(b.re, b.im);
+            for (int k = 0; k < 6; ++k) {
+                const typename SC::P* pl = Uk + (size_t)(w * 6 + k) * V;
+                const cx<typename SC::R> f = SC::ldb(pl, co(o_s)), b = SC::ldb(pl, co(ob));
+                uf[k] = {(double)f.re, (double)f.im};
+                ub[k] = {(double)b.re, (double)b.im};
+            }
+            third_row<double>(uf, invk, neg_f);
+            third_row<double>(ub, invk, neg_b);
+#pragma unroll
+            for (int k = 0; k < 9; ++k) {
+                sU[(2 * w) * 9 + k][lane] = make_double2(uf[k].re, uf[k].im);
+                sU[(2 * w + 1) * 9 + k][lane] = make_double2(ub[k].re, ub[k].im);
+            }
+        } else {
+#pragma unroll
+            for (int k = 0; k < 9; ++k) {
+                const typename SC::P* pl = Uk + (size_t)(w * 9 + k) * V;
+                const cx<typename SC::R> f = SC::ldb(pl, co(o_s)), b = SC::ldb(pl, co(ob));
+                sU[(2 * w) * 9 + k][lane] = make_double2((double)f.re, (double)f.im);
+                sU[(2 * w + 1) * 9 + k][lane] = make_double2((double)b.re, (double)b.im);
+            }
         }
         // the blocks are read by this tile only: streamed, so they do not take L2 room from the
         // neighbour spinors and links other tiles reuse (measured 1-2 % faster)
 #pragma unroll
         for (int j = 0; j < 9; ++j) {
-            const cx<double> v = StF64::ldb_nt(Cl + (size_t)(w * 9 + j) * V, o_s);
-            sT[w * 9 + j][lane] = make_double2(v.re, v.im);
+            const cx<typename SC::R> v = SC::ldb_nt(Cl + (size_t)(w * 9 + j) * V, co(o_s));
+            sT[w * 9 + j][lane] = make_double2((double)v.re, (double)v.im);
         }
     }
     __syncthreads();
@@ -835,14 +859,16 @@ hipError_t launch_hop_cols(const Geom& g, const LinkInfo& li, const void* Uk, co
 template <class SF, class SY, int MODE, class SC = SF>
 hipError_t launch_hop_t(const Geom& g, const LinkInfo& li, const void* Uk, const void* Cl, const void* X,
                         const void* Rh, void* Y, int L, hipStream_t s) {
-    if constexpr (std::is_same_v<SF, StF64> && std::is_same_v<SY, StF64> && std::is_same_v<SC, StF64>) {
-        // FP64 from three columns on: the LDS-staged kernel (measured faster at every L >= 3
-        // at 32^3 x 64; with one or two columns the staging cannot be shared by enough waves)
+    if constexpr (std::is_same_v<SF, StF64> && std::is_same_v<SY, StF64>) {
+        // FP64 vectors from three columns on: the LDS-staged kernel (measured faster at every
+        // L >= 3 at 32^3 x 64; with one or two columns the staging cannot be shared by enough
+        // waves); the links and blocks may be stored in FP32 or BF16 (SC)
         if (L >= 3) {
             const SiteMap sm = make_site_map_rows(g, 12.0 * L * 16 + 72.0 * 16);
             dim3 block(64, 4), grid(sm.nblk);
-            k_hop_f64<MODE><<<grid, block, 0, s>>>(g, sm, (const double2*)Uk, (const double2*)Cl, (const double2*)X,
-                                                  (const double2*)Rh, (double2*)Y, L);
+            k_hop_f64<MODE, 0, SC><<<grid, block, 0, s>>>(g, sm, (const typename SC::P*)Uk, (const typename SC::P*)Cl,
+                                                         (const double2*)X, (const double2*)Rh, (double2*)Y, L, li.invk,
+                                                         li.bc_t);
             return hipGetLastError();
         }
     }
@@ -894,17 +920,46 @@ hipError_t launch_sweep(const wd_ctx* c, int pi, const void* X, const void* Rh, 
 
 // One FP64 sweep of three or more columns with the iterates in the format FMT
 // (FMT_IN_TD / FMT_OUT_TD: time-diagonal input / output).
-template <int FMT>
+template <int FMT, class SC = StF64>
 hipError_t launch_sweep_td(const wd_ctx* c, const double2* X, const double2* R, double2* Y, int L, hipStream_t s) {
     const SiteMap sm = make_site_map_rows(c->g, 12.0 * L * 16 + 72.0 * 16);
     dim3 block(64, 4), grid(sm.nblk);
+    constexpr int pi = std::is_same_v<SC, StF64> ? 0 : std::is_same_v<SC, StF32> ? 1 : 2;
+    using PC = typename SC::P;
+    const LinkInfo li = link_info(c);
     if (c->jacobi_kind == WD_JACOBI_POINT)
-        k_hop_f64<JPOINT, FMT><<<grid, block, 0, s>>>(c->g, sm, (const double2*)c->f.Uk[0],
-                                                      (const double2*)c->f.Tp[0], X, R, Y, L);
+        k_hop_f64<JPOINT, FMT, SC><<<grid, block, 0, s>>>(c->g, sm, (const PC*)c->f.Uk[pi], (const PC*)c->f.Tp[pi], X,
+                                                          R, Y, L, li.invk, li.bc_t);
     else
-        k_hop_f64<JBLOCK, FMT><<<grid, block, 0, s>>>(c->g, sm, (const double2*)c->f.Uk[0],
-                                                      (const double2*)c->f.Ti[0], X, R, Y, L);
+        k_hop_f64<JBLOCK, FMT, SC><<<grid, block, 0, s>>>(c->g, sm, (const PC*)c->f.Uk[pi], (const PC*)c->f.Ti[pi], X,
+                                                          R, Y, L, li.invk, li.bc_t);
     return hipGetLastError();
+}
+
+// Sweeps 2 .. j of a Jacobi application with FP64 iterates (coefficients in SC): from three
+// columns on with the iterates between sweeps in the time-diagonal form, else in the standard
+// form through launch_sweep.  `first` holds the first sweep's output; the result lands in Z.
+template <class SC>
+hipError_t sweep_chain(wd_ctx* c, int pi, const double2* R, double2* Z, double2* tmp, double2* out, int L, int j,
+                       hipStream_t s) {
+    hipError_t e = hipSuccess;
+    for (int i = 2; i <= j && e == hipSuccess; ++i) {
+        double2* in = out;
+        out = ((j - i) % 2 == 0) ? Z : tmp;
+        if (L >= 3 && j >= 3) {
+            // the second sweep reads the standard output of the first, the last one writes Z in
+            // the standard form
+            if (i == 2)
+                e = launch_sweep_td<FMT_OUT_TD, SC>(c, in, R, out, L, s);
+            else if (i < j)
+                e = launch_sweep_td<FMT_IN_TD | FMT_OUT_TD, SC>(c, in, R, out, L, s);
+            else
+                e = launch_sweep_td<FMT_IN_TD, SC>(c, in, R, out, L, s);
+        } else {
+            e = launch_sweep<StF64, StF64, SC>(c, pi, in, R, out, L, s);
+        }
+    }
+    return e;
 }
 
 // j sweeps with FP64 vectors and arithmetic and the links and A_D^{-1} of
@@ -916,12 +971,8 @@ hipError_t jacobi_coef(wd_ctx* c, int pi, const double2* R, double2* Z, int L, i
     double2* tmp = c->ws[10];
     double2* out = ((j - 1) % 2 == 0) ? Z : tmp;
     hipError_t e = launch_first<StF64, StF64, StF64, SC>(c, clf, R, nullptr, out, L, s);
-    for (int i = 2; i <= j && e == hipSuccess; ++i) {
-        double2* in = out;
-        out = ((j - i) % 2 == 0) ? Z : tmp;
-        e = launch_sweep<StF64, StF64, SC>(c, pi, in, R, out, L, s);
-    }
-    return e;
+    if (e != hipSuccess) return e;
+    return sweep_chain<SC>(c, pi, R, Z, tmp, out, L, j, s);
 }
 
 // j sweeps in storage format S (FP32 or BF16), FP64 in and out.
@@ -956,8 +1007,13 @@ hipError_t launch_sweep_f64(const wd_ctx* c, const double2* X, const double2* R,
 
 hipError_t launch_sweep_coef(const wd_ctx* c, const double2* X, const double2* R, double2* Y, int L, Prec coef,
                              hipStream_t s) {
-    if (coef == Prec::F32) return launch_sweep<StF64, StF64, StF32>(c, 1, X, R, Y, L, s);
-    if (coef == Prec::BF16) return launch_sweep<StF64, StF64, StBF16>(c, 2, X, R, Y, L, s);
+    // as launch_sweep_f64: from three columns on, the middle sweep (time-diagonal in and out)
+    if (coef == Prec::F32)
+        return L >= 3 ? launch_sweep_td<FMT_IN_TD | FMT_OUT_TD, StF32>(c, X, R, Y, L, s)
+                      : launch_sweep<StF64, StF64, StF32>(c, 1, X, R, Y, L, s);
+    if (coef == Prec::BF16)
+        return L >= 3 ? launch_sweep_td<FMT_IN_TD | FMT_OUT_TD, StBF16>(c, X, R, Y, L, s)
+                      : launch_sweep<StF64, StF64, StBF16>(c, 2, X, R, Y, L, s);
     return hipErrorInvalidValue;
 }
 
@@ -989,24 +1045,7 @@ hipError_t launch_jacobi(wd_ctx* c, const double2* R, double2* Z, int L, int j, 
     double2* out = ((j - 1) % 2 == 0) ? Z : tmp;
     hipError_t e = launch_first<StF64, StF64, StF64>(c, clf, R, nullptr, out, L, s);
     if (e != hipSuccess) return e;
-    for (int i = 2; i <= j; ++i) {
-        double2* in = out;
-        out = ((j - i) % 2 == 0) ? Z : tmp;
-        if (L >= 3 && j >= 3) {
-            // iterates between sweeps in the time-diagonal form: the second sweep reads the
-            // standard output of the first, the last one writes Z in the standard form
-            if (i == 2)
-                e = launch_sweep_td<FMT_OUT_TD>(c, in, R, out, L, s);
-            else if (i < j)
-                e = launch_sweep_td<FMT_IN_TD | FMT_OUT_TD>(c, in, R, out, L, s);
-            else
-                e = launch_sweep_td<FMT_IN_TD>(c, in, R, out, L, s);
-        } else {
-            e = launch_sweep<StF64, StF64>(c, 0, in, R, out, L, s);
-        }
-        if (e != hipSuccess) return e;
-    }
-    return hipSuccess;
+    return sweep_chain<StF64>(c, 0, R, Z, tmp, out, L, j, s);
 }
 
 // Throughput measurement in FP32 / BF16 storage: X (and R) are rounded into
