@@ -432,6 +432,39 @@ def test_full_size_jacobi_two_sweeps_sampled_low_precision(pkg, big, prec, tol):
     assert err < tol
 
 
+@pytest.mark.parametrize("prec,tol", [("f64", 1e-13), ("f64c32", 9 * 2.0 ** -24), ("f64cbf16", 9 * 2.0 ** -8)])
+def test_full_size_jacobi_four_sweeps_sampled(pkg, big, prec, tol):
+    """j = 4 in the benchmark's launch configuration (32^3 x 64, twelve columns): between the
+    first and the last sweep the iterates are kept in the time-diagonal form (u + d, u - d), so
+    this runs all three forms of the sweep, among them the middle sweep bench.py times.  The
+    FP64 site operator recomputes G_k = T^-1 (R + kappa H G_{k-1}) on the dependence cone of the
+    sampled sites (three hops for G_1, two for G_2, one for G_3); FP64 iterates with rounded
+    coefficients are held to twice the per-sweep bound of their format (4.5 u)."""
+    w, c, U = big
+    V = wi.volume(w["dims"])
+    g = torch.Generator(device="cuda").manual_seed(12)
+    R = torch.complex(torch.randn((12, 12, V), generator=g, device="cuda", dtype=torch.float64),
+                      torch.randn((12, 12, V), generator=g, device="cuda", dtype=torch.float64))
+    Z = c.jacobi(R, 4, prec=prec)
+    so = SiteOperator(w["dims"], U, w["kappa"], w["csw"], w["bc_t"])
+    sites = _sample_sites(V, 2, 11)
+    cones = [set(sites)]
+    for _ in range(3):
+        cones.append(cones[-1] | {n for s in cones[-1] for (_, _, n, _) in so.neighbours(s)})
+    need = sorted(cones[-1])
+    Rs = R[:, :, torch.tensor(need, device="cuda")].cpu().numpy()
+    pos = {s: i for i, s in enumerate(need)}
+    Zs = Z[:, :, torch.tensor(sites, device="cuda")].cpu().numpy()
+    del R, Z
+    Tinv = {s: np.linalg.inv(so.T(s)) for s in need}
+    G = {s: Tinv[s] @ Rs[:, :, pos[s]].T for s in need}          # G_1 on the three-hop cone
+    for level in (2, 1, 0):
+        G = {s: Tinv[s] @ (Rs[:, :, pos[s]].T + w["kappa"] * so.hop_at(s, lambda t: G[t])) for s in cones[level]}
+    err = _maxrel(np.stack([Zs[:, :, k].T for k in range(len(sites))]), np.stack([G[s] for s in sites]))
+    _say(f"full-size Jacobi j=4 {prec}: {err:.2e} at {len(sites)} sites ({len(need)} in the cone)")
+    assert err < tol
+
+
 def test_kappa_zero_is_identity(pkg):
     """kappa = 0: A = 1, A_D = 1 and the operator and every Jacobi application return their
     input bit for bit; the solver then converges in one iteration with X = B to rounding."""
