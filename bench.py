@@ -553,7 +553,8 @@ def main():
         for kp in [kappa] + ([a.kappa_heavy] if a.kappa_heavy > 0 else []):
             ctx.set_params(kp, w["csw"])
             for j in (0, 4, 8, 12, 16, 24):
-                X, info = ctx.solve(B, tol=w["tol"], j=j, max_iter=3000)
+                # one run per j (no block splitting), as the paper's Table 2 counts iterations
+                X, info = ctx.solve(B, tol=w["tol"], j=j, max_iter=3000, no_split=True)
                 out[f"kappa{kp}_j{j}"] = {"status": info["status"], "iterations": info["iterations"],
                                           "mvm_paper_per_col": int(info["mvm_paper"]),
                                           "s_per_rhs": round(info["seconds"] / L, 5),
