@@ -100,8 +100,8 @@ def traffic_from_profiles(mode: int):
             return None
         for k, v in d.get("bytes_per_launch", {}).items():
             # the LDS-staged FP64 kernel (three or more columns): mode, iterate format (the timed
-            # sweep is the middle one, time-diagonal in and out: 3)
-            if k.startswith(f"void k_hop_f64<{mode}, {3 if mode == 1 else 0}>"):
+            # sweep is the middle one, time-diagonal in and out: 3), coefficient storage
+            if k.startswith(f"void k_hop_f64<{mode}, {3 if mode == 1 else 0}, StF64>"):
                 return v
         for k, v in d.get("bytes_per_launch", {}).items():
             # template arguments of the register-tiled hop kernel: storage in, storage out, columns,
