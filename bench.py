@@ -10,8 +10,9 @@ the timed region starts.
 Printed JSON line (one, from rank 0):
   value        algorithmic GB/s of the multi-RHS operator kernel Y = A X (the
                Dslash of the metric), timed with HIP events around back-to-back
-               launches on the library's stream; pct_hbm_peak is its fraction
-               of the 8 TB/s HBM peak
+               launches on the library's stream, on block vectors in the tiled
+               layout the solver runs in; pct_hbm_peak is its fraction of the
+               8 TB/s HBM peak
   solve_GBs    algorithmic HBM bytes of all kernels of the timed solves / time
   s_per_rhs    seconds per right-hand side of the timed solves
   roofline     the dominant kernel (the FP64 Jacobi sweep, 2j-2 of the 2j+2
@@ -100,8 +101,8 @@ def traffic_from_profiles(mode: int):
             return None
         for k, v in d.get("bytes_per_launch", {}).items():
             # the LDS-staged FP64 kernel (three or more columns): mode, iterate format (the timed
-            # sweep is the middle one, time-diagonal in and out: 3), coefficient storage
-            if k.startswith(f"void k_hop_f64<{mode}, {3 if mode == 1 else 0}, StF64>"):
+            # sweep is the middle one, time-diagonal in and out: 3), coefficient storage, tiled vectors
+            if k.startswith(f"void k_hop_f64<{mode}, {3 if mode == 1 else 0}, StF64, 1>"):
                 return v
         for k, v in d.get("bytes_per_launch", {}).items():
             # template arguments of the register-tiled hop kernel: storage in, storage out, columns,
@@ -115,10 +116,21 @@ def traffic_from_profiles(mode: int):
     return None
 
 
-def time_hop(ctx, torch, V, L, mode, reps, prec="f64"):
+def time_hop(ctx, torch, V, L, mode, reps, prec="f64", layout=None):
     """Average duration of one hopping-kernel launch (mode 0: A X, 1: Jacobi sweep), from HIP
     events on the library's stream around reps and 2 reps back-to-back launches (the difference
-    removes the once-per-call rounding of the inputs in FP32 / BF16)."""
+    removes the once-per-call rounding of the inputs in FP32 / BF16).  layout: the block-vector
+    layout of the launches; by default the tiled one the solver runs in when V allows it."""
+    if layout is None:
+        layout = "tiled" if V % 64 == 0 else "standard"
+    ctx.set_layout(layout)
+    try:
+        return _time_hop(ctx, torch, V, L, mode, reps, prec)
+    finally:
+        ctx.set_layout("standard")
+
+
+def _time_hop(ctx, torch, V, L, mode, reps, prec):
     g = torch.Generator(device="cuda").manual_seed(11)
     X = torch.complex(torch.randn((L, 12, V), generator=g, device="cuda", dtype=torch.float64),
                       torch.randn((L, 12, V), generator=g, device="cuda", dtype=torch.float64))
@@ -612,6 +624,10 @@ def main():
     # dominant kernel: the Jacobi sweep; also the operator kernel
     ms_sweep = time_hop(ctx, torch, V, L, 1, a.hop_reps)
     ms_apply = time_hop(ctx, torch, V, L, 0, a.hop_reps)
+    # the same kernels on block vectors in the standard layout (wd_apply / jacobi_precond of a
+    # caller who keeps it), for comparison
+    ms_sweep_std = time_hop(ctx, torch, V, L, 1, a.hop_reps, layout="standard")
+    ms_apply_std = time_hop(ctx, torch, V, L, 0, a.hop_reps, layout="standard")
     b_sweep = V * (1152 + 576 * L)
     b_apply = V * (1152 + 384 * L)
     ach = b_sweep / (ms_sweep / 1e3) / 1e9
@@ -619,12 +635,18 @@ def main():
     roof = {"bound": "hbm", "achieved": round(ach, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": round(ach / HBM_PEAK_GBS, 4), "traffic": traffic_from_profiles(1),
             "kernel": (f"k_hop_f64<JBLOCK, time-diagonal in and out> (middle Jacobi sweep, L={L})" if L >= 3 else f"k_hop<StF64,StF64,CT,JBLOCK> (Jacobi sweep, L={L})"),
+            "layout": "tiled" if V % 64 == 0 else "standard",
             "copy_GBs": round(copy_gbs, 1), "frac_of_copy": round(ach / copy_gbs, 4),
-            "avg_launch_ms": round(ms_sweep, 4), "alg_bytes_per_launch": b_sweep}
+            "avg_launch_ms": round(ms_sweep, 4), "alg_bytes_per_launch": b_sweep,
+            "standard_layout": {"avg_launch_ms": round(ms_sweep_std, 4),
+                                "frac": round(b_sweep / (ms_sweep_std / 1e3) / 1e9 / HBM_PEAK_GBS, 4)}}
     ach_a = b_apply / (ms_apply / 1e3) / 1e9
     dslash = {"achieved": round(ach_a, 1), "frac": round(ach_a / HBM_PEAK_GBS, 4), "unit": "GB/s",
               "avg_launch_ms": round(ms_apply, 4), "alg_bytes_per_launch": b_apply,
-              "traffic": traffic_from_profiles(0)}
+              "layout": "tiled" if V % 64 == 0 else "standard",
+              "traffic": traffic_from_profiles(0),
+              "standard_layout": {"avg_launch_ms": round(ms_apply_std, 4),
+                                  "frac": round(b_apply / (ms_apply_std / 1e3) / 1e9 / HBM_PEAK_GBS, 4)}}
 
     # time to solution per right-hand side: FP64 Jacobi (the plain form), low-precision Jacobi,
     # learned M, at the workload's kappa and at a heavier quark mass (kappa_heavy)

@@ -40,6 +40,8 @@ WD_LOSS_ERROR, WD_LOSS_RESIDUAL = 0, 1
 LOSS = {"error": WD_LOSS_ERROR, "residual": WD_LOSS_RESIDUAL}
 WD_JACOBI_BLOCK, WD_JACOBI_POINT = 0, 1
 WD_MAX_L = 16
+WD_LAYOUT_STANDARD, WD_LAYOUT_TILED = 0, 1
+LAYOUT = {"standard": WD_LAYOUT_STANDARD, "tiled": WD_LAYOUT_TILED}
 
 PREC = {"f64": WD_F64, "f32": WD_F32, "bf16": WD_BF16, "f64c32": WD_F64_COEF_F32, "f64cbf16": WD_F64_COEF_BF16}
 STATUS_NAME = {WD_OK: "converged", WD_NOT_CONVERGED: "not_converged", WD_BREAKDOWN: "breakdown",
@@ -77,6 +79,7 @@ SIGNATURES = [
     ("wd_set_links", c_int, [c_void_p, c_void_p, c_int]),
     ("wd_set_params", c_int, [c_void_p, c_double, c_double, c_int]),
     ("wd_get_clover", c_int, [c_void_p, c_int, c_void_p]),
+    ("wd_set_layout", c_int, [c_void_p, c_int]),
     ("wd_apply", c_int, [c_void_p, c_void_p, c_void_p, c_int, c_int]),
     ("jacobi_precond", c_int, [c_void_p, c_void_p, c_void_p, c_int, c_int, c_int]),
     ("bbicggr_solve", c_int, [c_void_p, c_void_p, c_void_p, c_int, c_double, POINTER(SolveOpts),
@@ -196,6 +199,12 @@ class Context:
         out = np.empty((self.V, 2, 6, 6), dtype=np.complex128)
         _check(self._lib.wd_get_clover(self._h, int(which), out.ctypes.data), "wd_get_clover")
         return out
+
+    def set_layout(self, layout: str):
+        """Row layout of the block vectors this context reads and writes: "standard"
+        (row k*V + s) or "tiled" (row (s//64)*768 + k*64 + s%64); tensors keep the shape
+        (L, 12, V) either way."""
+        _check(self._lib.wd_set_layout(self._h, LAYOUT[layout]), "wd_set_layout")
 
     # ---- hot path
     def _block(self, t, L=None):

@@ -146,6 +146,7 @@ int wd_destroy(wd_ctx* c) {
     }
     for (auto& w : c->ws) dev_free((void*&)w);
     for (auto& w : c->lp) dev_free(w);
+    for (auto& w : c->tb) dev_free((void*&)w);
     dev_free((void*&)c->partial);
     dev_free((void*&)c->small);
     dev_free((void*&)c->theta);
@@ -290,6 +291,13 @@ int wd_get_clover(wd_ctx* c, int which, double* out_host) {
                     m[j * 6 + i] = make_double2(o.x, -o.y);
                 }
         }
+    return WD_OK;
+}
+
+int wd_set_layout(wd_ctx* c, int layout) {
+    if (!c || (layout != WD_LAYOUT_STANDARD && layout != WD_LAYOUT_TILED)) return WD_EINVAL;
+    if (layout == WD_LAYOUT_TILED && !tiled_ok(c->g)) return WD_EINVAL;
+    c->g.vt = layout == WD_LAYOUT_TILED ? 1 : 0;
     return WD_OK;
 }
 
@@ -514,6 +522,7 @@ struct Driver {
     double bnorm[WD_MAX_L] = {};
     int iters = 0, total_iters = 0, restarts = 0, cycles = 0, snaps = 0, splits = 0, min_block = WD_MAX_L;
     bool fell_back = false;
+    bool snap_untile = false;  // the solve runs tiled for a standard-layout caller: snapshots go back
     double cond_max = 0.0;
     long long snap_clock = 0;
     int hist_pos = 0;
@@ -656,7 +665,11 @@ int solve_block(Driver& D, const double2* B, double2* X, int col0, int L, bool u
             iters = k + 1;
             ++D.snap_clock;
             if (whole && D.snaps < D.op.snap_count && D.snap_clock % D.op.snap_every == 0) {
-                WD_TRY_HIP(launch_copy((double2*)D.op.x_snap + (size_t)D.snaps * N * L, X, N * L, st));
+                double2* slot = (double2*)D.op.x_snap + (size_t)D.snaps * N * L;
+                if (D.snap_untile)
+                    WD_TRY_HIP(launch_retile(X, slot, c->g.V, L, false, st));
+                else
+                    WD_TRY_HIP(launch_copy(slot, X, N * L, st));
                 S.blocks(2);
                 ++D.snaps;
             }
@@ -988,6 +1001,7 @@ int solve_setup(wd_ctx* c, const void* Bv, void* Xv, int L, double tol, const wd
         return WD_EINVAL;
     if (op.precond == WD_PRECOND_LEARNED) {
         if (op.prec_inner == WD_BF16 || coef_prec(op.prec_inner)) return WD_EINVAL;
+        if (c->g.vt) return WD_EINVAL;  // the learned kernels take the standard layout only
         if (!c->have_theta) return WD_ESTATE;
         int r0 = learned_ensure(c);
         if (r0) return r0;
@@ -1032,6 +1046,17 @@ int solve_setup(wd_ctx* c, const void* Bv, void* Xv, int L, double tol, const wd
     return WD_OK;
 }
 
+// The two blocks a solve in the tiled layout needs for a caller of the standard
+// one, allocated on first use (a failed allocation is tried again next time).
+int tiled_ensure(wd_ctx* c) {
+    for (auto& b : c->tb) {
+        if (b) continue;
+        int r = dev_alloc((void**)&b, block_elems(c, c->max_L) * 16);
+        if (r) return r;
+    }
+    return WD_OK;
+}
+
 int solve_common(wd_ctx* c, const void* Bv, void* Xv, int L, double tol, const wd_solve_opts* o,
                  wd_solve_info* info, bool stab) {
     Driver D;
@@ -1040,7 +1065,24 @@ int solve_common(wd_ctx* c, const void* Bv, void* Xv, int L, double tol, const w
     const auto t0 = std::chrono::steady_clock::now();
     const double2* B = (const double2*)Bv;
     double2* X = (double2*)Xv;
+    // A caller of the standard layout gets the solve in the tiled one (its stencils run
+    // faster): B and X are copied into the tiled layout here, X back at the end and every
+    // snapshot as it is taken.  Not with the learned preconditioner, whose kernels take the
+    // standard layout only; without the two blocks of memory the solve stays in the standard
+    // layout.
+    const bool retile = !c->g.vt && tiled_ok(c->g) && D.S.precond != WD_PRECOND_LEARNED &&
+                        tiled_ensure(c) == WD_OK;
+    D.snap_untile = retile;
     rc = hipStreamSynchronize(c->stream) == hipSuccess ? WD_OK : WD_EHIP;
+    if (rc == WD_OK && retile) {
+        if (launch_retile(B, c->tb[0], c->g.V, L, true, c->stream) != hipSuccess ||
+            (D.op.use_x0 && launch_retile(X, c->tb[1], c->g.V, L, true, c->stream) != hipSuccess))
+            rc = WD_EHIP;
+        D.S.blocks(D.op.use_x0 ? 4 : 2);
+        B = c->tb[0];
+        X = c->tb[1];
+        c->g.vt = 1;
+    }
     if (rc == WD_OK) {
         double bn2[WD_MAX_L];
         rc = D.S.norms(B, bn2);
@@ -1050,7 +1092,16 @@ int solve_common(wd_ctx* c, const void* Bv, void* Xv, int L, double tol, const w
             else D.bnorm[i] = std::sqrt(bn2[i]);
         }
     }
-    if (rc == WD_OK) rc = stab ? stab_solve(D, B, X, D.op.use_x0 != 0) : solve_block(D, B, X, 0, L, D.op.use_x0 != 0);
+    const bool ran = rc == WD_OK;
+    if (ran) rc = stab ? stab_solve(D, B, X, D.op.use_x0 != 0) : solve_block(D, B, X, 0, L, D.op.use_x0 != 0);
+    if (retile) {
+        // X back into the caller's layout, whatever the outcome of the iteration
+        c->g.vt = 0;
+        if (ran) {
+            if (launch_retile(X, (double2*)Xv, c->g.V, L, false, c->stream) != hipSuccess && rc >= 0) rc = WD_EHIP;
+            D.S.blocks(2);
+        }
+    }
     if (hipStreamSynchronize(c->stream) != hipSuccess && rc >= 0) rc = WD_EHIP;
     const double secs = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
     fill_info(D, rc, secs, L, info);

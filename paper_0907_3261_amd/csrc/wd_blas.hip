@@ -654,6 +654,20 @@ __global__ void k_fill0(double2* __restrict__ d, size_t n) {
     if (i < n) d[i] = make_double2(0.0, 0.0);
 }
 
+// Block vector of L columns between the standard layout (row k*V + s) and the
+// tiled one (row (s/64)*768 + k*64 + s%64); one thread per element of the tiled
+// side, so each 64-site run of a plane is one 1 KB read or write on both sides.
+template <bool TO_TILED>
+__global__ void k_retile(const double2* __restrict__ in, double2* __restrict__ out, size_t V, size_t n) {
+    const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const size_t N = 12 * V, col = i / N, r = i - col * N;
+    const size_t tile = r / 768, k = (r % 768) / 64, s = tile * 64 + (r % 64);
+    const size_t std_i = col * N + k * V + s;
+    if (TO_TILED) out[i] = in[std_i];
+    else out[std_i] = in[i];
+}
+
 // ---------------------------------------------------------------------------
 // Block BiCGSTAB helpers (the foil of block BiCGGR)
 // ---------------------------------------------------------------------------
@@ -848,6 +862,16 @@ hipError_t launch_copy(double2* dst, const double2* src, size_t n, hipStream_t s
 
 hipError_t launch_zero(double2* dst, size_t n, hipStream_t s) {
     k_fill0<<<nblk(n, 256), 256, 0, s>>>(dst, n);
+    return hipGetLastError();
+}
+
+hipError_t launch_retile(const double2* src, double2* dst, size_t V, int L, bool to_tiled, hipStream_t s) {
+    if (V % 64 != 0) return hipErrorInvalidValue;
+    const size_t n = (size_t)12 * V * L;
+    if (to_tiled)
+        k_retile<true><<<nblk(n, 256), 256, 0, s>>>(src, dst, V, n);
+    else
+        k_retile<false><<<nblk(n, 256), 256, 0, s>>>(src, dst, V, n);
     return hipGetLastError();
 }
 

@@ -174,13 +174,14 @@ __device__ __forceinline__ void third_row(cx<R> (&u)[9], R invk, bool neg) {
 // One hop direction for the CT columns of this thread: the link is loaded
 // once and applied to every column.  Xc is the wave-uniform base of the
 // thread's first column; link_off and nb_off are byte offsets of the link's
-// site and of the neighbour site inside one plane.  SC: storage of the links
+// site and of the neighbour site inside one plane; V and KS are the plane
+// strides of the links and of the block vector.  SC: storage of the links
 // (widened to the compute type of S on load; FP32 and BF16 links are stored
 // as two rows, planes [mu][6][V], and completed by third_row).
 template <class S, int MU, bool FWD, bool ADD, int CT, bool NT = false, class SC = S>
 __device__ __forceinline__ void hop_all(cx<typename S::R> (&acc)[CT][12], const typename SC::P* __restrict__ Uk,
                                         const typename S::P* __restrict__ Xc, uint32_t link_off, uint32_t nb_off,
-                                        size_t V, typename S::R invk = 0, bool neg = false) {
+                                        size_t V, size_t KS, typename S::R invk = 0, bool neg = false) {
     using R = typename S::R;
     // keep each direction's loads and arithmetic together: without this fence
     // the scheduler hoists the loads of all eight directions and spills
@@ -205,7 +206,7 @@ __device__ __forceinline__ void hop_all(cx<typename S::R> (&acc)[CT][12], const 
         cx<R> p[12];
         const typename S::P* xc = Xc + (size_t)c * 12 * V;
 #pragma unroll
-        for (int k = 0; k < 12; ++k) p[k] = NT ? S::ldb_nt(xc + (size_t)k * V, nb_off) : S::ldb(xc + (size_t)k * V, nb_off);
+        for (int k = 0; k < 12; ++k) p[k] = NT ? S::ldb_nt(xc + (size_t)k * KS, nb_off) : S::ldb(xc + (size_t)k * KS, nb_off);
         hop_dir<R, MU, FWD, ADD>(acc[c], u, p);
     }
 }
@@ -234,27 +235,34 @@ __global__ void __launch_bounds__(256)
     if (tile >= ntiles || s < 0) return;
     const int c0 = col_begin + tile * CT;
     const size_t V = g.V;
-    const size_t cs = 12 * V;  // column stride
+    const size_t cs = 12 * V;        // column stride of a block vector
+    const size_t KS = vec_plane(g);  // its plane stride (standard or tiled layout)
 
     const int x = s % g.lx;
     const int y = (s / g.lx) % g.ly;
     const int z = (s / g.sxy) % g.lz;
     const int t = s / g.sxyz;
+    const int n_bx = (x == 0) ? s + (g.lx - 1) : s - 1;
+    const int n_by = (y == 0) ? s + (g.ly - 1) * g.lx : s - g.lx;
+    const int n_bz = (z == 0) ? s + (g.lz - 1) * g.sxy : s - g.sxy;
+    const int n_bt = (t == 0) ? s + (g.lt - 1) * g.sxyz : s - g.sxyz;
+    // byte offsets of the sites in a plane of the block vector
     const uint32_t PB = sizeof(PF);
-    const uint32_t o_s = (uint32_t)s * PB;
-    const uint32_t o_y = (uint32_t)s * (uint32_t)sizeof(PY);  // the output may have another pair size
-    const uint32_t o_fx = (uint32_t)((x == g.lx - 1) ? s - (g.lx - 1) : s + 1) * PB;
-    const uint32_t o_bx = (uint32_t)((x == 0) ? s + (g.lx - 1) : s - 1) * PB;
-    const uint32_t o_fy = (uint32_t)((y == g.ly - 1) ? s - (g.ly - 1) * g.lx : s + g.lx) * PB;
-    const uint32_t o_by = (uint32_t)((y == 0) ? s + (g.ly - 1) * g.lx : s - g.lx) * PB;
-    const uint32_t o_fz = (uint32_t)((z == g.lz - 1) ? s - (g.lz - 1) * g.sxy : s + g.sxy) * PB;
-    const uint32_t o_bz = (uint32_t)((z == 0) ? s + (g.lz - 1) * g.sxy : s - g.sxy) * PB;
-    const uint32_t o_ft = (uint32_t)((t == g.lt - 1) ? s - (g.lt - 1) * g.sxyz : s + g.sxyz) * PB;
-    const uint32_t o_bt = (uint32_t)((t == 0) ? s + (g.lt - 1) * g.sxyz : s - g.sxyz) * PB;
+    const auto vo = [&](int n) -> uint32_t { return vec_site(g, n) * PB; };
+    const uint32_t o_s = vo(s);
+    const uint32_t o_y = vec_site(g, s) * (uint32_t)sizeof(PY);  // the output may have another pair size
+    const uint32_t o_fx = vo((x == g.lx - 1) ? s - (g.lx - 1) : s + 1);
+    const uint32_t o_bx = vo(n_bx);
+    const uint32_t o_fy = vo((y == g.ly - 1) ? s - (g.ly - 1) * g.lx : s + g.lx);
+    const uint32_t o_by = vo(n_by);
+    const uint32_t o_fz = vo((z == g.lz - 1) ? s - (g.lz - 1) * g.sxy : s + g.sxy);
+    const uint32_t o_bz = vo(n_bz);
+    const uint32_t o_ft = vo((t == g.lt - 1) ? s - (g.lt - 1) * g.sxyz : s + g.sxyz);
+    const uint32_t o_bt = vo(n_bt);
     const PF* Xc = X + (size_t)c0 * cs;
     // byte offsets of the same sites in the coefficient arrays
     constexpr uint32_t PC = sizeof(typename SC::P);
-    const auto co = [](uint32_t o) -> uint32_t { return PC == sizeof(PF) ? o : (o / (uint32_t)sizeof(PF)) * PC; };
+    const auto co = [](int n) -> uint32_t { return (uint32_t)n * PC; };
 
     cx<R> acc[CT][12];
     if (MODE == APPLY) {
@@ -262,12 +270,12 @@ __global__ void __launch_bounds__(256)
 #pragma unroll
         for (int chir = 0; chir < 2; ++chir) {
             Herm6<SC, R> T;
-            T.template load<(NTP & 1) != 0>(Cl, chir, co(o_s), V);
+            T.template load<(NTP & 1) != 0>(Cl, chir, co(s), V);
 #pragma unroll
             for (int c = 0; c < CT; ++c) {
                 cx<R> v[6];
 #pragma unroll
-                for (int k = 0; k < 6; ++k) v[k] = SF::ldb(Xc + (size_t)c * cs + (size_t)(6 * chir + k) * V, o_s);
+                for (int k = 0; k < 6; ++k) v[k] = SF::ldb(Xc + (size_t)c * cs + (size_t)(6 * chir + k) * KS, o_s);
 #pragma unroll
                 for (int i = 0; i < 6; ++i) {
                     cx<R> r = {R(0), R(0)};
@@ -283,7 +291,7 @@ __global__ void __launch_bounds__(256)
         for (int c = 0; c < CT; ++c) {
 #pragma unroll
             for (int k = 0; k < 12; ++k)
-                acc[c][k] = SF::ldb_nt(Rc + (size_t)c * cs + (size_t)k * V, o_s);
+                acc[c][k] = SF::ldb_nt(Rc + (size_t)c * cs + (size_t)k * KS, o_s);
         }
     }
 
@@ -292,14 +300,14 @@ __global__ void __launch_bounds__(256)
     // (the forward link of t = Lt - 1, the backward link seen from t = 0)
     const R invk = (R)invk_d;
     const bool neg_ft = bc_t && t == g.lt - 1, neg_bt = bc_t && t == 0;
-    hop_all<SF, 0, true, ADD, CT, false, SC>(acc, Uk, Xc, co(o_s), o_fx, V, invk);
-    hop_all<SF, 0, false, ADD, CT, false, SC>(acc, Uk, Xc, co(o_bx), o_bx, V, invk);
-    hop_all<SF, 1, true, ADD, CT, false, SC>(acc, Uk, Xc, co(o_s), o_fy, V, invk);
-    hop_all<SF, 1, false, ADD, CT, false, SC>(acc, Uk, Xc, co(o_by), o_by, V, invk);
-    hop_all<SF, 2, true, ADD, CT, false, SC>(acc, Uk, Xc, co(o_s), o_fz, V, invk);
-    hop_all<SF, 2, false, ADD, CT, false, SC>(acc, Uk, Xc, co(o_bz), o_bz, V, invk);
-    hop_all<SF, 3, true, ADD, CT, (NTP & 2) != 0, SC>(acc, Uk, Xc, co(o_s), o_ft, V, invk, neg_ft);
-    hop_all<SF, 3, false, ADD, CT, (NTP & 2) != 0, SC>(acc, Uk, Xc, co(o_bt), o_bt, V, invk, neg_bt);
+    hop_all<SF, 0, true, ADD, CT, false, SC>(acc, Uk, Xc, co(s), o_fx, V, KS, invk);
+    hop_all<SF, 0, false, ADD, CT, false, SC>(acc, Uk, Xc, co(n_bx), o_bx, V, KS, invk);
+    hop_all<SF, 1, true, ADD, CT, false, SC>(acc, Uk, Xc, co(s), o_fy, V, KS, invk);
+    hop_all<SF, 1, false, ADD, CT, false, SC>(acc, Uk, Xc, co(n_by), o_by, V, KS, invk);
+    hop_all<SF, 2, true, ADD, CT, false, SC>(acc, Uk, Xc, co(s), o_fz, V, KS, invk);
+    hop_all<SF, 2, false, ADD, CT, false, SC>(acc, Uk, Xc, co(n_bz), o_bz, V, KS, invk);
+    hop_all<SF, 3, true, ADD, CT, (NTP & 2) != 0, SC>(acc, Uk, Xc, co(s), o_ft, V, KS, invk, neg_ft);
+    hop_all<SF, 3, false, ADD, CT, (NTP & 2) != 0, SC>(acc, Uk, Xc, co(n_bt), o_bt, V, KS, invk, neg_bt);
     __builtin_amdgcn_sched_barrier(0);
 
     PY* Yc = Y + (size_t)c0 * cs;
@@ -307,12 +315,12 @@ __global__ void __launch_bounds__(256)
 #pragma unroll
         for (int c = 0; c < CT; ++c)
 #pragma unroll
-            for (int k = 0; k < 12; ++k) store_out<SY>(Yc + (size_t)c * cs + (size_t)k * V, o_y, acc[c][k]);
+            for (int k = 0; k < 12; ++k) store_out<SY>(Yc + (size_t)c * cs + (size_t)k * KS, o_y, acc[c][k]);
     } else {
 #pragma unroll
         for (int chir = 0; chir < 2; ++chir) {
             Herm6<SC, R> T;
-            T.template load<(NTP & 1) != 0>(Cl, chir, co(o_s), V);
+            T.template load<(NTP & 1) != 0>(Cl, chir, co(s), V);
 #pragma unroll
             for (int c = 0; c < CT; ++c) {
                 {
@@ -320,7 +328,7 @@ __global__ void __launch_bounds__(256)
                     if (MODE == JPOINT) {
 #pragma unroll
                         for (int k = 0; k < 6; ++k)
-                            xs[k] = SF::ldb(Xc + (size_t)c * cs + (size_t)(6 * chir + k) * V, o_s);
+                            xs[k] = SF::ldb(Xc + (size_t)c * cs + (size_t)(6 * chir + k) * KS, o_s);
                     }
 #pragma unroll
                     for (int i = 0; i < 6; ++i) {
@@ -337,7 +345,7 @@ __global__ void __launch_bounds__(256)
                                 if (j != i) q = q - T.at(i, j) * xs[j];
                             r = T.d[i] * q;
                         }
-                        store_out<SY>(Yc + (size_t)c * cs + (size_t)(6 * chir + i) * V, o_y, r);
+                        store_out<SY>(Yc + (size_t)c * cs + (size_t)(6 * chir + i) * KS, o_y, r);
                     }
                 }
             }
@@ -383,7 +391,7 @@ enum { FMT_IN_TD = 1, FMT_OUT_TD = 2 };
 // neighbour reuse of a column within the XCD's L2.  FMT: time-diagonal input
 // and / or output (sweeps only); with FMT = 0 the arithmetic and its order
 // are k_hop's (bit-identical results).
-template <int MODE, int FMT = 0, class SC = StF64>
+template <int MODE, int FMT = 0, class SC = StF64, int VT = 0>
 __global__ void __launch_bounds__(256)
     k_hop_f64(const Geom g, const SiteMap sm, const typename SC::P* __restrict__ Uk,
               const typename SC::P* __restrict__ Cl, const double2* __restrict__ X, const double2* __restrict__ Rh,
@@ -402,32 +410,39 @@ __global__ void __launch_bounds__(256)
     // which keeps the stores unpredicated (a predicated store doubles the register use here)
     const int s = s0 >= 0 ? s0 : map_site(g, sm, blockIdx.x, 0);
     const size_t V = g.V;
-    const size_t cs = 12 * V;
+    const size_t cs = 12 * V;         // column stride of a block vector
+    // the block-vector layout is a template argument here (VT = g.vt), so that the plane
+    // stride of the tiled layout is a constant of the address arithmetic
+    const size_t KS = VT ? (size_t)64 : V;  // plane stride of a block vector
+    const auto vsite = [](int n) -> uint32_t { return VT ? (uint32_t)((n >> 6) * 768 + (n & 63)) : (uint32_t)n; };
     const int x = s % g.lx, y = (s / g.lx) % g.ly, z = (s / g.sxy) % g.lz, t = s / g.sxyz;
     constexpr uint32_t PB = 16;
-    uint32_t on[8];  // byte offsets of the neighbours x+, x-, y+, y-, z+, z-, t+, t-
-    on[0] = (uint32_t)((x == g.lx - 1) ? s - (g.lx - 1) : s + 1) * PB;
-    on[1] = (uint32_t)((x == 0) ? s + (g.lx - 1) : s - 1) * PB;
-    on[2] = (uint32_t)((y == g.ly - 1) ? s - (g.ly - 1) * g.lx : s + g.lx) * PB;
-    on[3] = (uint32_t)((y == 0) ? s + (g.ly - 1) * g.lx : s - g.lx) * PB;
-    on[4] = (uint32_t)((z == g.lz - 1) ? s - (g.lz - 1) * g.sxy : s + g.sxy) * PB;
-    on[5] = (uint32_t)((z == 0) ? s + (g.lz - 1) * g.sxy : s - g.sxy) * PB;
-    on[6] = (uint32_t)((t == g.lt - 1) ? s - (g.lt - 1) * g.sxyz : s + g.sxyz) * PB;
-    on[7] = (uint32_t)((t == 0) ? s + (g.lt - 1) * g.sxyz : s - g.sxyz) * PB;
-    const uint32_t o_s = (uint32_t)s * PB;
+    int nb[8];  // the neighbours x+, x-, y+, y-, z+, z-, t+, t-
+    nb[0] = (x == g.lx - 1) ? s - (g.lx - 1) : s + 1;
+    nb[1] = (x == 0) ? s + (g.lx - 1) : s - 1;
+    nb[2] = (y == g.ly - 1) ? s - (g.ly - 1) * g.lx : s + g.lx;
+    nb[3] = (y == 0) ? s + (g.ly - 1) * g.lx : s - g.lx;
+    nb[4] = (z == g.lz - 1) ? s - (g.lz - 1) * g.sxy : s + g.sxy;
+    nb[5] = (z == 0) ? s + (g.lz - 1) * g.sxy : s - g.sxy;
+    nb[6] = (t == g.lt - 1) ? s - (g.lt - 1) * g.sxyz : s + g.sxyz;
+    nb[7] = (t == 0) ? s + (g.lt - 1) * g.sxyz : s - g.sxyz;
+    uint32_t on[8];  // byte offsets of the neighbours' spinors inside a plane of a column
+#pragma unroll
+    for (int d = 0; d < 8; ++d) on[d] = vsite(nb[d]) * PB;
+    const uint32_t o_s = vsite(s) * PB;
     {
         // coefficient fields in storage SC: FP64, or FP32 / BF16 (two-row links, completed by
         // third_row, and 6x6 blocks, all widened to FP64 here, once per tile)
         constexpr uint32_t PC = sizeof(typename SC::P);
-        const auto co = [](uint32_t o) -> uint32_t { return (o / PB) * PC; };
-        const uint32_t ob = (w == 0) ? on[1] : (w == 1) ? on[3] : (w == 2) ? on[5] : on[7];
+        const int sb = (w == 0) ? nb[1] : (w == 1) ? nb[3] : (w == 2) ? nb[5] : nb[7];
+        const uint32_t c_s = (uint32_t)s * PC, c_b = (uint32_t)sb * PC;
         if constexpr (kCompressedLinks<SC>) {
             const bool neg_f = (w == 3) && bc_t && t == g.lt - 1, neg_b = (w == 3) && bc_t && t == 0;
             cx<double> uf[9], ub[9];
 #pragma unroll
             for (int k = 0; k < 6; ++k) {
                 const typename SC::P* pl = Uk + (size_t)(w * 6 + k) * V;
-                const cx<typename SC::R> f = SC::ldb(pl, co(o_s)), b = SC::ldb(pl, co(ob));
+                const cx<typename SC::R> f = SC::ldb(pl, c_s), b = SC::ldb(pl, c_b);
                 uf[k] = {(double)f.re, (double)f.im};
                 ub[k] = {(double)b.re, (double)b.im};
             }
@@ -442,7 +457,7 @@ __global__ void __launch_bounds__(256)
 #pragma unroll
             for (int k = 0; k < 9; ++k) {
                 const typename SC::P* pl = Uk + (size_t)(w * 9 + k) * V;
-                const cx<typename SC::R> f = SC::ldb(pl, co(o_s)), b = SC::ldb(pl, co(ob));
+                const cx<typename SC::R> f = SC::ldb(pl, c_s), b = SC::ldb(pl, c_b);
                 sU[(2 * w) * 9 + k][lane] = make_double2((double)f.re, (double)f.im);
                 sU[(2 * w + 1) * 9 + k][lane] = make_double2((double)b.re, (double)b.im);
             }
@@ -451,7 +466,7 @@ __global__ void __launch_bounds__(256)
         // neighbour spinors and links other tiles reuse (measured 1-2 % faster)
 #pragma unroll
         for (int j = 0; j < 9; ++j) {
-            const cx<typename SC::R> v = SC::ldb_nt(Cl + (size_t)(w * 9 + j) * V, co(o_s));
+            const cx<typename SC::R> v = SC::ldb_nt(Cl + (size_t)(w * 9 + j) * V, c_s);
             sT[w * 9 + j][lane] = make_double2((double)v.re, (double)v.im);
         }
     }
@@ -471,7 +486,7 @@ __global__ void __launch_bounds__(256)
                 herm_from_lds(T, sT, chir, ln);
                 cx<double> v[6];
 #pragma unroll
-                for (int k = 0; k < 6; ++k) v[k] = StF64::ldb(xc + (size_t)(6 * chir + k) * V, o_s);
+                for (int k = 0; k < 6; ++k) v[k] = StF64::ldb(xc + (size_t)(6 * chir + k) * KS, o_s);
 #pragma unroll
                 for (int i = 0; i < 6; ++i) {
                     cx<double> r = {0.0, 0.0};
@@ -483,7 +498,7 @@ __global__ void __launch_bounds__(256)
         } else {
             const double2* rc = Rh + (size_t)c * cs;
 #pragma unroll
-            for (int k = 0; k < 12; ++k) acc[k] = StF64::ldb_nt(rc + (size_t)k * V, o_s);
+            for (int k = 0; k < 12; ++k) acc[k] = StF64::ldb_nt(rc + (size_t)k * KS, o_s);
         }
         // neighbour spinor of direction d (time-direction neighbours are streamed, as in k_hop);
         // in the time-diagonal form the time hops load only the half they project onto
@@ -492,12 +507,12 @@ __global__ void __launch_bounds__(256)
             if (TD_IN && d >= 6) {
                 const int k0 = (d == 6) ? 6 : 0;  // t+: b = u - d, t-: a = u + d
 #pragma unroll
-                for (int k = 0; k < 6; ++k) dst[k] = StF64::ldb_nt(xc + (size_t)(k0 + k) * V, on[d]);
+                for (int k = 0; k < 6; ++k) dst[k] = StF64::ldb_nt(xc + (size_t)(k0 + k) * KS, on[d]);
                 return;
             }
 #pragma unroll
             for (int k = 0; k < 12; ++k)
-                dst[k] = (d >= 6) ? StF64::ldb_nt(xc + (size_t)k * V, on[d]) : StF64::ldb(xc + (size_t)k * V, on[d]);
+                dst[k] = (d >= 6) ? StF64::ldb_nt(xc + (size_t)k * KS, on[d]) : StF64::ldb(xc + (size_t)k * KS, on[d]);
         };
         load_dir(p[0], 0);
         static_for<0, 8>([&](auto dc) {
@@ -531,7 +546,7 @@ __global__ void __launch_bounds__(256)
         double2* yc = Y + (size_t)c * cs;
         if (MODE == APPLY) {
 #pragma unroll
-            for (int k = 0; k < 12; ++k) StF64::stb_nt(yc + (size_t)k * V, o_s, acc[k]);
+            for (int k = 0; k < 12; ++k) StF64::stb_nt(yc + (size_t)k * KS, o_s, acc[k]);
         } else {
             cx<double> out[12];
 #pragma unroll
@@ -544,13 +559,13 @@ __global__ void __launch_bounds__(256)
                         // own site, back to the standard form: u = (a + b) / 2, d = (a - b) / 2
 #pragma unroll
                         for (int k = 0; k < 6; ++k) {
-                            const cx<double> av = StF64::ldb(xc + (size_t)k * V, o_s);
-                            const cx<double> bv = StF64::ldb(xc + (size_t)(k + 6) * V, o_s);
+                            const cx<double> av = StF64::ldb(xc + (size_t)k * KS, o_s);
+                            const cx<double> bv = StF64::ldb(xc + (size_t)(k + 6) * KS, o_s);
                             xs[k] = chir == 0 ? 0.5 * (av + bv) : 0.5 * (av - bv);
                         }
                     } else {
 #pragma unroll
-                        for (int k = 0; k < 6; ++k) xs[k] = StF64::ldb(xc + (size_t)(6 * chir + k) * V, o_s);
+                        for (int k = 0; k < 6; ++k) xs[k] = StF64::ldb(xc + (size_t)(6 * chir + k) * KS, o_s);
                     }
                 }
 #pragma unroll
@@ -571,15 +586,15 @@ __global__ void __launch_bounds__(256)
                     if constexpr (TD_OUT) {
                         out[6 * chir + i] = r;
                     } else {
-                        StF64::stb_nt(yc + (size_t)(6 * chir + i) * V, o_s, r);
+                        StF64::stb_nt(yc + (size_t)(6 * chir + i) * KS, o_s, r);
                     }
                 }
             }
             if constexpr (TD_OUT) {
 #pragma unroll
                 for (int k = 0; k < 6; ++k) {
-                    StF64::stb_nt(yc + (size_t)k * V, o_s, out[k] + out[k + 6]);
-                    StF64::stb_nt(yc + (size_t)(k + 6) * V, o_s, out[k] - out[k + 6]);
+                    StF64::stb_nt(yc + (size_t)k * KS, o_s, out[k] + out[k + 6]);
+                    StF64::stb_nt(yc + (size_t)(k + 6) * KS, o_s, out[k] - out[k + 6]);
                 }
             }
         }
@@ -609,30 +624,35 @@ __global__ void __launch_bounds__(256)
     // a lane without a site takes lane 0's site (unpredicated stores, as in k_hop_f64)
     const int s = s0 >= 0 ? s0 : map_site(g, sm, blockIdx.x, 0);
     const size_t V = g.V;
-    const size_t cs = 12 * V;
+    const size_t cs = 12 * V;         // column stride of a block vector
+    const size_t KS = vec_plane(g);   // its plane stride (standard or tiled layout)
     const int x = s % g.lx, y = (s / g.lx) % g.ly, z = (s / g.sxy) % g.lz, t = s / g.sxyz;
     constexpr uint32_t PB = sizeof(PF);
-    uint32_t on[8];
-    on[0] = (uint32_t)((x == g.lx - 1) ? s - (g.lx - 1) : s + 1) * PB;
-    on[1] = (uint32_t)((x == 0) ? s + (g.lx - 1) : s - 1) * PB;
-    on[2] = (uint32_t)((y == g.ly - 1) ? s - (g.ly - 1) * g.lx : s + g.lx) * PB;
-    on[3] = (uint32_t)((y == 0) ? s + (g.ly - 1) * g.lx : s - g.lx) * PB;
-    on[4] = (uint32_t)((z == g.lz - 1) ? s - (g.lz - 1) * g.sxy : s + g.sxy) * PB;
-    on[5] = (uint32_t)((z == 0) ? s + (g.lz - 1) * g.sxy : s - g.sxy) * PB;
-    on[6] = (uint32_t)((t == g.lt - 1) ? s - (g.lt - 1) * g.sxyz : s + g.sxyz) * PB;
-    on[7] = (uint32_t)((t == 0) ? s + (g.lt - 1) * g.sxyz : s - g.sxyz) * PB;
-    const uint32_t o_s = (uint32_t)s * PB;
+    int nb[8];  // the neighbours x+, x-, y+, y-, z+, z-, t+, t-
+    nb[0] = (x == g.lx - 1) ? s - (g.lx - 1) : s + 1;
+    nb[1] = (x == 0) ? s + (g.lx - 1) : s - 1;
+    nb[2] = (y == g.ly - 1) ? s - (g.ly - 1) * g.lx : s + g.lx;
+    nb[3] = (y == 0) ? s + (g.ly - 1) * g.lx : s - g.lx;
+    nb[4] = (z == g.lz - 1) ? s - (g.lz - 1) * g.sxy : s + g.sxy;
+    nb[5] = (z == 0) ? s + (g.lz - 1) * g.sxy : s - g.sxy;
+    nb[6] = (t == g.lt - 1) ? s - (g.lt - 1) * g.sxyz : s + g.sxyz;
+    nb[7] = (t == 0) ? s + (g.lt - 1) * g.sxyz : s - g.sxyz;
+    uint32_t on[8];  // byte offsets of the neighbours' spinors inside a plane of a column
+#pragma unroll
+    for (int d = 0; d < 8; ++d) on[d] = vec_site(g, nb[d]) * PB;
+    const uint32_t o_s = vec_site(g, s) * PB;
+    const uint32_t c_s = (uint32_t)s * PB;  // the site in the coefficient fields
     {
         // wave mu: the two stored rows of U_mu(x) and U_mu(x - mu), completed by third_row (the
         // antiperiodic sign of the time links on the last slice, seen from t = Lt - 1 forward and
         // from t = 0 backward), then stored in LDS as full 3 x 3 float matrices
-        const uint32_t ob = (w == 0) ? on[1] : (w == 1) ? on[3] : (w == 2) ? on[5] : on[7];
+        const uint32_t ob = (uint32_t)((w == 0) ? nb[1] : (w == 1) ? nb[3] : (w == 2) ? nb[5] : nb[7]) * PB;
         const bool neg_f = (w == 3) && bc_t && t == g.lt - 1, neg_b = (w == 3) && bc_t && t == 0;
         cx<R> uf[9], ub[9];
 #pragma unroll
         for (int k = 0; k < 6; ++k) {
             const PF* pl = Uk + (size_t)(w * 6 + k) * V;
-            uf[k] = SF::ldb(pl, o_s);
+            uf[k] = SF::ldb(pl, c_s);
             ub[k] = SF::ldb(pl, ob);
         }
         third_row<R>(uf, invk, neg_f);
@@ -644,7 +664,7 @@ __global__ void __launch_bounds__(256)
         }
 #pragma unroll
         for (int j = 0; j < 9; ++j) {
-            const cx<R> v = SF::ldb_nt(Cl + (size_t)(w * 9 + j) * V, o_s);
+            const cx<R> v = SF::ldb_nt(Cl + (size_t)(w * 9 + j) * V, c_s);
             sT[w * 9 + j][lane] = make_float2(v.re, v.im);
         }
     }
@@ -675,7 +695,7 @@ __global__ void __launch_bounds__(256)
                 herm(T, chir);
                 cx<R> v[6];
 #pragma unroll
-                for (int k = 0; k < 6; ++k) v[k] = SF::ldb(xc + (size_t)(6 * chir + k) * V, o_s);
+                for (int k = 0; k < 6; ++k) v[k] = SF::ldb(xc + (size_t)(6 * chir + k) * KS, o_s);
 #pragma unroll
                 for (int i = 0; i < 6; ++i) {
                     cx<R> r = {R(0), R(0)};
@@ -687,13 +707,13 @@ __global__ void __launch_bounds__(256)
         } else {
             const PF* rc = Rh + (size_t)c * cs;
 #pragma unroll
-            for (int k = 0; k < 12; ++k) acc[k] = SF::ldb_nt(rc + (size_t)k * V, o_s);
+            for (int k = 0; k < 12; ++k) acc[k] = SF::ldb_nt(rc + (size_t)k * KS, o_s);
         }
         cx<R> p[2][12];
         auto load_dir = [&](cx<R>(&dst)[12], int d) {
 #pragma unroll
             for (int k = 0; k < 12; ++k)
-                dst[k] = (d >= 6) ? SF::ldb_nt(xc + (size_t)k * V, on[d]) : SF::ldb(xc + (size_t)k * V, on[d]);
+                dst[k] = (d >= 6) ? SF::ldb_nt(xc + (size_t)k * KS, on[d]) : SF::ldb(xc + (size_t)k * KS, on[d]);
         };
         load_dir(p[0], 0);
         static_for<0, 8>([&](auto dc) {
@@ -710,10 +730,10 @@ __global__ void __launch_bounds__(256)
         });
         __builtin_amdgcn_sched_barrier(0);
         typename SY::P* yc = Y + (size_t)c * cs;
-        const uint32_t o_y = (uint32_t)s * (uint32_t)sizeof(typename SY::P);
+        const uint32_t o_y = vec_site(g, s) * (uint32_t)sizeof(typename SY::P);
         if (MODE == APPLY) {
 #pragma unroll
-            for (int k = 0; k < 12; ++k) store_out<SY>(yc + (size_t)k * V, o_y, acc[k]);
+            for (int k = 0; k < 12; ++k) store_out<SY>(yc + (size_t)k * KS, o_y, acc[k]);
         } else {
 #pragma unroll
             for (int chir = 0; chir < 2; ++chir) {
@@ -722,7 +742,7 @@ __global__ void __launch_bounds__(256)
                 cx<R> xs[6];
                 if (MODE == JPOINT) {
 #pragma unroll
-                    for (int k = 0; k < 6; ++k) xs[k] = SF::ldb(xc + (size_t)(6 * chir + k) * V, o_s);
+                    for (int k = 0; k < 6; ++k) xs[k] = SF::ldb(xc + (size_t)(6 * chir + k) * KS, o_s);
                 }
 #pragma unroll
                 for (int i = 0; i < 6; ++i) {
@@ -738,7 +758,7 @@ __global__ void __launch_bounds__(256)
                             if (j != i) q = q - T.at(i, j) * xs[j];
                         r = T.d[i] * q;
                     }
-                    store_out<SY>(yc + (size_t)(6 * chir + i) * V, o_y, r);
+                    store_out<SY>(yc + (size_t)(6 * chir + i) * KS, o_y, r);
                 }
             }
         }
@@ -759,10 +779,12 @@ __global__ void __launch_bounds__(256)
     const size_t V = g.V;
     const int s = blockIdx.x * 256 + threadIdx.x;
     if (s >= g.V) return;
-    const size_t cs = 12 * V;
-    const uint32_t oF = (uint32_t)s * sizeof(typename SF::P);
-    const uint32_t oI = (uint32_t)s * sizeof(typename SI::P);
-    const uint32_t oY = (uint32_t)s * sizeof(typename SY::P);
+    const size_t cs = 12 * V;        // column stride of a block vector
+    const size_t KS = vec_plane(g);  // its plane stride (standard or tiled layout)
+    const uint32_t vs = vec_site(g, s);
+    const uint32_t oF = vs * sizeof(typename SF::P);
+    const uint32_t oI = vs * sizeof(typename SI::P);
+    const uint32_t oY = vs * sizeof(typename SY::P);
     const uint32_t oC = (uint32_t)s * sizeof(typename SC::P);
 #pragma unroll
     for (int chir = 0; chir < 2; ++chir) {
@@ -773,11 +795,11 @@ __global__ void __launch_bounds__(256)
             cx<R> v[6];
 #pragma unroll
             for (int k = 0; k < 6; ++k) {
-                const auto w = SI::ldb_nt(Rc + (size_t)(6 * chir + k) * V, oI);
+                const auto w = SI::ldb_nt(Rc + (size_t)(6 * chir + k) * KS, oI);
                 v[k] = {(R)w.re, (R)w.im};
                 if (RL != nullptr) {
                     // later sweeps read the rounded copy; use the same rounded value here
-                    SF::stb(RL + (size_t)col * cs + (size_t)(6 * chir + k) * V, oF, v[k]);
+                    SF::stb(RL + (size_t)col * cs + (size_t)(6 * chir + k) * KS, oF, v[k]);
                     v[k] = SF::rnd(v[k]);
                 }
             }
@@ -790,7 +812,7 @@ __global__ void __launch_bounds__(256)
                 } else {
                     o = T.d[r] * v[r];
                 }
-                store_out<SY>(Y + (size_t)col * cs + (size_t)(6 * chir + r) * V, oY, o);
+                store_out<SY>(Y + (size_t)col * cs + (size_t)(6 * chir + r) * KS, oY, o);
             }
         }
     }
@@ -866,9 +888,14 @@ hipError_t launch_hop_t(const Geom& g, const LinkInfo& li, const void* Uk, const
         if (L >= 3) {
             const SiteMap sm = make_site_map_rows(g, 12.0 * L * 16 + 72.0 * 16);
             dim3 block(64, 4), grid(sm.nblk);
-            k_hop_f64<MODE, 0, SC><<<grid, block, 0, s>>>(g, sm, (const typename SC::P*)Uk, (const typename SC::P*)Cl,
-                                                         (const double2*)X, (const double2*)Rh, (double2*)Y, L, li.invk,
-                                                         li.bc_t);
+            if (g.vt)
+                k_hop_f64<MODE, 0, SC, 1><<<grid, block, 0, s>>>(
+                    g, sm, (const typename SC::P*)Uk, (const typename SC::P*)Cl, (const double2*)X,
+                    (const double2*)Rh, (double2*)Y, L, li.invk, li.bc_t);
+            else
+                k_hop_f64<MODE, 0, SC, 0><<<grid, block, 0, s>>>(
+                    g, sm, (const typename SC::P*)Uk, (const typename SC::P*)Cl, (const double2*)X,
+                    (const double2*)Rh, (double2*)Y, L, li.invk, li.bc_t);
             return hipGetLastError();
         }
     }
@@ -927,12 +954,17 @@ hipError_t launch_sweep_td(const wd_ctx* c, const double2* X, const double2* R, 
     constexpr int pi = std::is_same_v<SC, StF64> ? 0 : std::is_same_v<SC, StF32> ? 1 : 2;
     using PC = typename SC::P;
     const LinkInfo li = link_info(c);
-    if (c->jacobi_kind == WD_JACOBI_POINT)
-        k_hop_f64<JPOINT, FMT, SC><<<grid, block, 0, s>>>(c->g, sm, (const PC*)c->f.Uk[pi], (const PC*)c->f.Tp[pi], X,
-                                                          R, Y, L, li.invk, li.bc_t);
+    const bool pt = c->jacobi_kind == WD_JACOBI_POINT;
+    const PC* U = (const PC*)c->f.Uk[pi];
+    const PC* C = (const PC*)(pt ? c->f.Tp[pi] : c->f.Ti[pi]);
+    if (pt && c->g.vt)
+        k_hop_f64<JPOINT, FMT, SC, 1><<<grid, block, 0, s>>>(c->g, sm, U, C, X, R, Y, L, li.invk, li.bc_t);
+    else if (pt)
+        k_hop_f64<JPOINT, FMT, SC, 0><<<grid, block, 0, s>>>(c->g, sm, U, C, X, R, Y, L, li.invk, li.bc_t);
+    else if (c->g.vt)
+        k_hop_f64<JBLOCK, FMT, SC, 1><<<grid, block, 0, s>>>(c->g, sm, U, C, X, R, Y, L, li.invk, li.bc_t);
     else
-        k_hop_f64<JBLOCK, FMT, SC><<<grid, block, 0, s>>>(c->g, sm, (const PC*)c->f.Uk[pi], (const PC*)c->f.Ti[pi], X,
-                                                          R, Y, L, li.invk, li.bc_t);
+        k_hop_f64<JBLOCK, FMT, SC, 0><<<grid, block, 0, s>>>(c->g, sm, U, C, X, R, Y, L, li.invk, li.bc_t);
     return hipGetLastError();
 }
 

@@ -175,6 +175,7 @@ struct Geom {
     int V;          // number of sites
     int sxy;        // lx*ly
     int sxyz;       // lx*ly*lz
+    int vt = 0;     // block vectors in the tiled layout (below); needs V % 64 == 0
 };
 
 // Device data layouts (all "pair" arrays, site index fastest):
@@ -182,10 +183,24 @@ struct Geom {
 //   clover     [chirality c][18][V]         per 6x6 Hermitian block: entries
 //              0..2 hold the six real diagonal elements as (d0,d1),(d2,d3),(d4,d5),
 //              entries 3..17 the upper off-diagonal elements (i<j) in row order
-//   block vec  [column][k = 3*spin+colour][V]
+//   block vec  standard: [column][k = 3*spin+colour][V]
+//              tiled:    [column][V/64][k][64]: the 12 planes of a 64-site tile of a
+//              column are contiguous (12 KB in FP64), so a tile's spinors touch one
+//              memory page instead of twelve planes 16 V bytes apart.  Within a
+//              column it is a permutation of the rows, so the block updates, Grams and
+//              norms, which treat a column as a plain vector, work on either layout.
 __host__ __device__ constexpr int herm_index(int i, int j) {  // i < j, 6x6
     return i * 6 - i * (i + 1) / 2 + (j - i - 1);
 }
+
+// Element offset of site s inside a column of a block vector (plane k adds k times
+// vec_plane), in the layout of g.
+__host__ __device__ __forceinline__ uint32_t vec_site(const Geom& g, int s) {
+    return g.vt ? (uint32_t)((s >> 6) * 768 + (s & 63)) : (uint32_t)s;
+}
+__host__ __device__ __forceinline__ size_t vec_plane(const Geom& g) { return g.vt ? (size_t)64 : (size_t)g.V; }
+// the tiled layout needs whole tiles and 32-bit byte offsets inside an FP64 column
+inline bool tiled_ok(const Geom& g) { return g.V % 64 == 0 && (long long)g.V * 192 <= 0xFFFFFFFFLL; }
 
 // Workgroup index -> tile index such that each of the 8 XCDs (which receive
 // workgroups round-robin) works on one contiguous range of tiles.
@@ -207,23 +222,25 @@ __device__ __forceinline__ int xcd_remap(int b, int nb) {
 // between XCDs, whose neighbours are processed at the same time.  Lattices
 // with Lz * Ly too small for the split use contiguous site ranges.
 struct SiteMap {
-    int mode;   // 1: XCD sub-lattices, 0: contiguous ranges
-    int ny;     // y split
-    int nz;     // z split
-    int tpp;    // 64-site tiles per plane of a sub-lattice (max over XCDs)
-    int nblk;   // workgroups in the grid
+    int mode;    // 1: XCD sub-lattices, 0: contiguous ranges
+    int ny;      // y split
+    int nz;      // z split
+    int tpp;     // 64-site tiles per plane of a sub-lattice (max over XCDs)
+    int nblk;    // workgroups in the grid
+    int nt = 1;  // t split (ny * nz * nt = 8)
 };
 
 // Site of this lane, or -1.
 __device__ __forceinline__ int map_site(const Geom& g, const SiteMap& m, int b, int lane) {
     if (m.mode == 1) {
         const int k = b & 7, i = b >> 3;
-        const int ky = k % m.ny, kz = k / m.ny;
+        const int ky = k % m.ny, kr = k / m.ny, kz = kr % m.nz, kt = kr / m.nz;
         const int y0 = (ky * g.ly) / m.ny, ny = ((ky + 1) * g.ly) / m.ny - y0;
         const int z0 = (kz * g.lz) / m.nz, nz = ((kz + 1) * g.lz) / m.nz - z0;
+        const int t0 = (kt * g.lt) / m.nt, nt = ((kt + 1) * g.lt) / m.nt - t0;
         const int plane = i / m.tpp, tip = i - plane * m.tpp;
-        if (plane >= nz * g.lt) return -1;
-        const int t = plane / nz, z = z0 + (plane - t * nz);
+        if (plane >= nz * nt) return -1;
+        const int tt = plane / nz, z = z0 + (plane - tt * nz), t = t0 + tt;
         const int xy = tip * 64 + lane;
         if (xy >= g.lx * ny) return -1;
         const int y = y0 + xy / g.lx, x = xy - (xy / g.lx) * g.lx;
@@ -307,6 +324,8 @@ struct wd_ctx {
     double2* ws[12] = {};
     // low-precision Jacobi iterates: two ping-pong blocks and the right-hand side copy
     void* lp[3] = {};
+    // B and X of a solve run in the tiled layout for a caller of the standard one
+    double2* tb[2] = {};
     // reduction partials and small control data
     double2* partial = nullptr;
     int n_partial_blocks = 0;
@@ -411,5 +430,7 @@ hipError_t launch_colnorms(const double2* R, size_t N, int L, double2* partial, 
                            hipStream_t s);
 hipError_t launch_copy(double2* dst, const double2* src, size_t n, hipStream_t s);
 hipError_t launch_zero(double2* dst, size_t n, hipStream_t s);
+// an L-column block vector from the standard into the tiled layout (to_tiled) or back
+hipError_t launch_retile(const double2* src, double2* dst, size_t V, int L, bool to_tiled, hipStream_t s);
 
 }  // namespace wd

@@ -292,7 +292,10 @@ def test_solve_every_block_width(pkg, L):
 
 
 def test_solve_point_sources_jacobi_oracle_residual(pkg):
-    """8^3 x 16, kappa 0.135, c_SW 1.6, twelve point sources, Jacobi j = 4, 8, 12, 16."""
+    """8^3 x 16, kappa 0.135, c_SW 1.6, twelve point sources, Jacobi j = 4, 8, 12, 16.  Here
+    rho(kappa T^-1 H) = 1.047 > 1, so the longer Jacobi chains amplify rounding and a run may
+    fail and be continued on halves of the block (splits); the cost formula of Table 1 is
+    checked for the solves made of one run."""
     w, c, op = _workload_ctx(pkg, "lat8x16_L12_point")
     B = wi.point_block(op.V, 12)
     Bm = op.block_to_mat(B)
@@ -303,9 +306,10 @@ def test_solve_point_sources_jacobi_oracle_residual(pkg):
         # independent check with the oracle's operator
         tr = true_residual(op.A_mat, Bm, op.block_to_mat(_host(X)))
         assert np.max(tr) <= 1e-12
-        if info["restarts"] == 0:
+        if info["restarts"] == 0 and info["splits"] == 0:
             assert info["mvm_paper"] == 2 * (j + 1) * info["iterations"] + 1
-        _say(f"j={j}: k={info['iterations']} mvm/L={info['mvm_paper']} restarts={info['restarts']}")
+        _say(f"j={j}: k={info['iterations']} mvm/L={info['mvm_paper']} restarts={info['restarts']} "
+             f"splits={info['splits']}")
     c.close()
 
 
