@@ -228,6 +228,7 @@ struct SiteMap {
     int tpp;     // 64-site tiles per plane of a sub-lattice (max over XCDs)
     int nblk;    // workgroups in the grid
     int nt = 1;  // t split (ny * nz * nt = 8)
+    int tb = 1;  // t-slices walked together: planes go (t block, z, t within the block)
 };
 
 // Site of this lane, or -1.
@@ -240,7 +241,12 @@ __device__ __forceinline__ int map_site(const Geom& g, const SiteMap& m, int b, 
         const int t0 = (kt * g.lt) / m.nt, nt = ((kt + 1) * g.lt) / m.nt - t0;
         const int plane = i / m.tpp, tip = i - plane * m.tpp;
         if (plane >= nz * nt) return -1;
-        const int tt = plane / nz, z = z0 + (plane - tt * nz), t = t0 + tt;
+        // planes in blocks of tb t-slices: within a block z-plane by z-plane, the tb slices of
+        // a z-plane one after the other (tb = 1: slice by slice); a last partial block is
+        // shorter
+        const int blk = plane / (nz * m.tb), r = plane - blk * (nz * m.tb);
+        const int tbn = nt - blk * m.tb < m.tb ? nt - blk * m.tb : m.tb;
+        const int z = z0 + r / tbn, t = t0 + blk * m.tb + (r - (r / tbn) * tbn);
         const int xy = tip * 64 + lane;
         if (xy >= g.lx * ny) return -1;
         const int y = y0 + xy / g.lx, x = xy - (xy / g.lx) * g.lx;
@@ -274,8 +280,10 @@ inline SiteMap make_site_map(const Geom& g, double bytes_site) {
 // Site map of the LDS-staged kernels: the finest y split (y x z = 8 x 1, then
 // 4 x 2, ...) whose per-XCD planes still hold whole 64-site tiles, so that an
 // XCD walks few rows of every z-plane, plane by plane (measured 3 % faster than
-// the L2-budget split at 32^3 x 64, L = 12); else the budget rule above.
-inline SiteMap make_site_map_rows(const Geom& g, double bytes_site) {
+// the L2-budget split at 32^3 x 64, L = 12); else the budget rule above.  With
+// tb > 1 the XCD walks tb t-slices together, so a site's time neighbours inside
+// the block are read while still in the L2.
+inline SiteMap make_site_map_rows(const Geom& g, double bytes_site, int tb = 1) {
     for (int ny = 8; ny >= 1; ny /= 2) {
         const int nz = 8 / ny;
         if (g.ly % ny != 0 || g.lz < nz) continue;
@@ -287,6 +295,7 @@ inline SiteMap make_site_map_rows(const Geom& g, double bytes_site) {
         m.nz = nz;
         m.tpp = g.lx * rows / 64;
         m.nblk = 8 * ((g.lz + nz - 1) / nz) * g.lt * m.tpp;
+        m.tb = tb < 1 ? 1 : (tb > g.lt ? g.lt : tb);
         return m;
     }
     return make_site_map(g, bytes_site);
