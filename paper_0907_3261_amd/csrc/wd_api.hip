@@ -243,6 +243,8 @@ int wd_set_params(wd_ctx* c, double kappa, double csw, int jacobi_kind) {
     const size_t V = c->g.V, links = (size_t)36 * V, clov = (size_t)36 * V;
     const size_t psize[3] = {16, 8, 4};
     hipStream_t s = c->stream;
+    c->have_params = false;
+    c->g.vt &= ~kCoefTiled;  // the fields below are written in the standard layout, then tiled
     double2* Ti64 = (double2*)c->f.Ti[0];
     WD_TRY_HIP(launch_clover(c->f.U, c->f.T, Ti64, c->g, kappa, csw, s));
     WD_TRY_HIP(launch_point_form(c->f.T, (double2*)c->f.Tp[0], V, s));
@@ -258,6 +260,26 @@ int wd_set_params(wd_ctx* c, double kappa, double csw, int jacobi_kind) {
         WD_TRY_HIP(launch_convert(Ti64, c->f.Ti[p], pr, 1.0, clov, s));
         WD_TRY_HIP(launch_convert((const double2*)c->f.Tp[0], c->f.Tp[p], pr, 1.0, clov, s));
         WD_TRY_HIP(launch_convert(c->f.T, c->f.Tc[p], pr, 1.0, clov, s));
+    }
+    // the hop kernels' FP64 fields in the tiled layout: each 64-site tile's links and 6x6 blocks
+    // one contiguous run (see coef_site); f.T, which wd_get_clover returns, stays standard.
+    // The copy goes through an idle workspace block (no allocation here: a large temporary
+    // freed before the low-precision blocks are allocated was measured to slow the BF16
+    // sweep by 40 %); with max_L < 3 that block is too small and the fields stay standard.
+    void* tmp = block_elems(c, c->max_L) >= clov ? (void*)c->ws[WS_T2] : nullptr;
+    if (coef_tiled_ok(c->g) && tmp) {
+        hipError_t e = hipSuccess;
+        auto tile = [&](void* f, int np, int pb) {
+            if (e == hipSuccess) e = launch_tile_field(f, tmp, V, np, pb, s);
+            if (e == hipSuccess) e = hipMemcpyAsync(f, tmp, (size_t)np * V * pb, hipMemcpyDeviceToDevice, s);
+        };
+        tile(c->f.Uk[0], 36, 16);
+        tile(c->f.Ti[0], 36, 16);
+        tile(c->f.Tp[0], 36, 16);
+        tile(c->f.Tc[0], 36, 16);
+        if (e == hipSuccess) e = hipStreamSynchronize(s);
+        if (e != hipSuccess) return WD_EHIP;
+        c->g.vt |= kCoefTiled;
     }
     WD_TRY_HIP(hipStreamSynchronize(s));
     c->kappa = kappa;
@@ -276,17 +298,22 @@ int wd_get_clover(wd_ctx* c, int which, double* out_host) {
     WD_TRY_HIP(hipMemcpyAsync(packed.data(), src, 36 * V * 16, hipMemcpyDeviceToHost, c->stream));
     WD_TRY_HIP(hipStreamSynchronize(c->stream));
     double2* out = (double2*)out_host;
+    // T^{-1} is one of the hop kernels' fields, kept tiled when the lattice allows it
+    const bool tiled = which == 1 && (c->g.vt & kCoefTiled);
+    auto at = [&](size_t plane, size_t s) -> const double2& {
+        return tiled ? packed[((s / 64) * 36 + plane) * 64 + s % 64] : packed[plane * V + s];
+    };
     for (size_t s = 0; s < V; ++s)
         for (int ch = 0; ch < 2; ++ch) {
             double2* m = out + (s * 2 + ch) * 36;
             for (int i = 0; i < 3; ++i) {
-                const double2 d = packed[(ch * 18 + i) * V + s];
+                const double2 d = at(ch * 18 + i, s);
                 m[(2 * i) * 6 + 2 * i] = make_double2(d.x, 0.0);
                 m[(2 * i + 1) * 6 + 2 * i + 1] = make_double2(d.y, 0.0);
             }
             for (int i = 0; i < 6; ++i)
                 for (int j = i + 1; j < 6; ++j) {
-                    const double2 o = packed[(ch * 18 + 3 + herm_index(i, j)) * V + s];
+                    const double2 o = at(ch * 18 + 3 + herm_index(i, j), s);
                     m[i * 6 + j] = o;
                     m[j * 6 + i] = make_double2(o.x, -o.y);
                 }
@@ -297,7 +324,7 @@ int wd_get_clover(wd_ctx* c, int which, double* out_host) {
 int wd_set_layout(wd_ctx* c, int layout) {
     if (!c || (layout != WD_LAYOUT_STANDARD && layout != WD_LAYOUT_TILED)) return WD_EINVAL;
     if (layout == WD_LAYOUT_TILED && !tiled_ok(c->g)) return WD_EINVAL;
-    c->g.vt = layout == WD_LAYOUT_TILED ? 1 : 0;
+    c->g.vt = (c->g.vt & ~kVecTiled) | (layout == WD_LAYOUT_TILED ? kVecTiled : 0);
     return WD_OK;
 }
 
@@ -1001,7 +1028,7 @@ int solve_setup(wd_ctx* c, const void* Bv, void* Xv, int L, double tol, const wd
         return WD_EINVAL;
     if (op.precond == WD_PRECOND_LEARNED) {
         if (op.prec_inner == WD_BF16 || coef_prec(op.prec_inner)) return WD_EINVAL;
-        if (c->g.vt) return WD_EINVAL;  // the learned kernels take the standard layout only
+        if (c->g.vt & kVecTiled) return WD_EINVAL;  // the learned kernels take the standard layout only
         if (!c->have_theta) return WD_ESTATE;
         int r0 = learned_ensure(c);
         if (r0) return r0;
@@ -1070,7 +1097,7 @@ int solve_common(wd_ctx* c, const void* Bv, void* Xv, int L, double tol, const w
     // snapshot as it is taken.  Not with the learned preconditioner, whose kernels take the
     // standard layout only; without the two blocks of memory the solve stays in the standard
     // layout.
-    const bool retile = !c->g.vt && tiled_ok(c->g) && D.S.precond != WD_PRECOND_LEARNED &&
+    const bool retile = !(c->g.vt & kVecTiled) && tiled_ok(c->g) && D.S.precond != WD_PRECOND_LEARNED &&
                         tiled_ensure(c) == WD_OK;
     D.snap_untile = retile;
     rc = hipStreamSynchronize(c->stream) == hipSuccess ? WD_OK : WD_EHIP;
@@ -1081,7 +1108,7 @@ int solve_common(wd_ctx* c, const void* Bv, void* Xv, int L, double tol, const w
         D.S.blocks(D.op.use_x0 ? 4 : 2);
         B = c->tb[0];
         X = c->tb[1];
-        c->g.vt = 1;
+        c->g.vt |= kVecTiled;
     }
     if (rc == WD_OK) {
         double bn2[WD_MAX_L];
@@ -1096,7 +1123,7 @@ int solve_common(wd_ctx* c, const void* Bv, void* Xv, int L, double tol, const w
     if (ran) rc = stab ? stab_solve(D, B, X, D.op.use_x0 != 0) : solve_block(D, B, X, 0, L, D.op.use_x0 != 0);
     if (retile) {
         // X back into the caller's layout, whatever the outcome of the iteration
-        c->g.vt = 0;
+        c->g.vt &= ~kVecTiled;
         if (ran) {
             if (launch_retile(X, (double2*)Xv, c->g.V, L, false, c->stream) != hipSuccess && rc >= 0) rc = WD_EHIP;
             D.S.blocks(2);

@@ -654,6 +654,16 @@ __global__ void k_fill0(double2* __restrict__ d, size_t n) {
     if (i < n) d[i] = make_double2(0.0, 0.0);
 }
 
+// A coefficient field [np][V] into the tiled order [V/64][np][64]; one thread per
+// element of the output.
+template <typename T>
+__global__ void k_tile_field(const T* __restrict__ in, T* __restrict__ out, size_t V, int np) {
+    const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= V * (size_t)np) return;
+    const size_t tile = i / ((size_t)np * 64), r = i - tile * np * 64, p = r / 64;
+    out[i] = in[p * V + tile * 64 + (r % 64)];
+}
+
 // Block vector of L columns between the standard layout (row k*V + s) and the
 // tiled one (row (s/64)*768 + k*64 + s%64); one thread per element of the tiled
 // side, so each 64-site run of a plane is one 1 KB read or write on both sides.
@@ -862,6 +872,18 @@ hipError_t launch_copy(double2* dst, const double2* src, size_t n, hipStream_t s
 
 hipError_t launch_zero(double2* dst, size_t n, hipStream_t s) {
     k_fill0<<<nblk(n, 256), 256, 0, s>>>(dst, n);
+    return hipGetLastError();
+}
+
+hipError_t launch_tile_field(const void* src, void* dst, size_t V, int np, int pair_bytes, hipStream_t s) {
+    if (V % 64 != 0) return hipErrorInvalidValue;
+    const size_t n = V * (size_t)np;
+    switch (pair_bytes) {
+        case 16: k_tile_field<double2><<<nblk(n, 256), 256, 0, s>>>((const double2*)src, (double2*)dst, V, np); break;
+        case 8: k_tile_field<float2><<<nblk(n, 256), 256, 0, s>>>((const float2*)src, (float2*)dst, V, np); break;
+        case 4: k_tile_field<uint32_t><<<nblk(n, 256), 256, 0, s>>>((const uint32_t*)src, (uint32_t*)dst, V, np); break;
+        default: return hipErrorInvalidValue;
+    }
     return hipGetLastError();
 }
 

@@ -174,14 +174,17 @@ __device__ __forceinline__ void third_row(cx<R> (&u)[9], R invk, bool neg) {
 // One hop direction for the CT columns of this thread: the link is loaded
 // once and applied to every column.  Xc is the wave-uniform base of the
 // thread's first column; link_off and nb_off are byte offsets of the link's
-// site and of the neighbour site inside one plane; V and KS are the plane
-// strides of the links and of the block vector.  SC: storage of the links
+// site and of the neighbour site inside one plane; V is the number of sites
+// (the plane stride of the links and 12 V the column stride of the block
+// vector), KS the block vector's plane stride.  LT: the links may be tiled
+// (FP64 fields), with their plane stride in LS (V, or 64 when tiled).  SC: storage of the links
 // (widened to the compute type of S on load; FP32 and BF16 links are stored
 // as two rows, planes [mu][6][V], and completed by third_row).
-template <class S, int MU, bool FWD, bool ADD, int CT, bool NT = false, class SC = S>
+template <class S, int MU, bool FWD, bool ADD, int CT, bool NT = false, class SC = S, bool LT = false>
 __device__ __forceinline__ void hop_all(cx<typename S::R> (&acc)[CT][12], const typename SC::P* __restrict__ Uk,
                                         const typename S::P* __restrict__ Xc, uint32_t link_off, uint32_t nb_off,
-                                        size_t V, size_t KS, typename S::R invk = 0, bool neg = false) {
+                                        size_t V, size_t KS, typename S::R invk = 0, bool neg = false,
+                                        size_t LS = 0) {
     using R = typename S::R;
     // keep each direction's loads and arithmetic together: without this fence
     // the scheduler hoists the loads of all eight directions and spills
@@ -190,14 +193,14 @@ __device__ __forceinline__ void hop_all(cx<typename S::R> (&acc)[CT][12], const 
     if constexpr (kCompressedLinks<SC>) {
 #pragma unroll
         for (int k = 0; k < 6; ++k) {
-            const cx<typename SC::R> v = SC::ldb(Uk + (size_t)(MU * 6 + k) * V, link_off);
+            const cx<typename SC::R> v = SC::ldb(Uk + (size_t)(MU * 6 + k) * (LT ? LS : V), link_off);
             u[k] = {(R)v.re, (R)v.im};
         }
         third_row<R>(u, invk, neg);
     } else {
 #pragma unroll
         for (int k = 0; k < 9; ++k) {
-            const cx<typename SC::R> v = SC::ldb(Uk + (size_t)(MU * 9 + k) * V, link_off);
+            const cx<typename SC::R> v = SC::ldb(Uk + (size_t)(MU * 9 + k) * (LT ? LS : V), link_off);
             u[k] = {(R)v.re, (R)v.im};
         }
     }
@@ -260,9 +263,18 @@ __global__ void __launch_bounds__(256)
     const uint32_t o_ft = vo((t == g.lt - 1) ? s - (g.lt - 1) * g.sxyz : s + g.sxyz);
     const uint32_t o_bt = vo(n_bt);
     const PF* Xc = X + (size_t)c0 * cs;
-    // byte offsets of the same sites in the coefficient arrays
+    // byte offsets of the same sites in the coefficient fields (links: co, 36 planes; 6x6
+    // blocks: cb, 36 planes) and their plane stride CKS.  Only FP64 fields may be tiled (LT);
+    // the FP32 / BF16 instantiations keep the plain site addressing, whose generated code is
+    // the faster one for the VALU-bound BF16 sweep.
     constexpr uint32_t PC = sizeof(typename SC::P);
-    const auto co = [](int n) -> uint32_t { return (uint32_t)n * PC; };
+    constexpr bool LT = PC == 16;
+    const size_t CKS = LT ? coef_plane<PC>(g) : V;
+    const auto co = [&](int n) -> uint32_t {
+        if constexpr (LT) return coef_site<PC>(g, n, 36) * PC;
+        else return (uint32_t)n * PC;
+    };
+    const auto cb = co;
 
     cx<R> acc[CT][12];
     if (MODE == APPLY) {
@@ -270,7 +282,7 @@ __global__ void __launch_bounds__(256)
 #pragma unroll
         for (int chir = 0; chir < 2; ++chir) {
             Herm6<SC, R> T;
-            T.template load<(NTP & 1) != 0>(Cl, chir, co(s), V);
+            T.template load<(NTP & 1) != 0>(Cl, chir, cb(s), CKS);
 #pragma unroll
             for (int c = 0; c < CT; ++c) {
                 cx<R> v[6];
@@ -300,14 +312,14 @@ __global__ void __launch_bounds__(256)
     // (the forward link of t = Lt - 1, the backward link seen from t = 0)
     const R invk = (R)invk_d;
     const bool neg_ft = bc_t && t == g.lt - 1, neg_bt = bc_t && t == 0;
-    hop_all<SF, 0, true, ADD, CT, false, SC>(acc, Uk, Xc, co(s), o_fx, V, KS, invk);
-    hop_all<SF, 0, false, ADD, CT, false, SC>(acc, Uk, Xc, co(n_bx), o_bx, V, KS, invk);
-    hop_all<SF, 1, true, ADD, CT, false, SC>(acc, Uk, Xc, co(s), o_fy, V, KS, invk);
-    hop_all<SF, 1, false, ADD, CT, false, SC>(acc, Uk, Xc, co(n_by), o_by, V, KS, invk);
-    hop_all<SF, 2, true, ADD, CT, false, SC>(acc, Uk, Xc, co(s), o_fz, V, KS, invk);
-    hop_all<SF, 2, false, ADD, CT, false, SC>(acc, Uk, Xc, co(n_bz), o_bz, V, KS, invk);
-    hop_all<SF, 3, true, ADD, CT, (NTP & 2) != 0, SC>(acc, Uk, Xc, co(s), o_ft, V, KS, invk, neg_ft);
-    hop_all<SF, 3, false, ADD, CT, (NTP & 2) != 0, SC>(acc, Uk, Xc, co(n_bt), o_bt, V, KS, invk, neg_bt);
+    hop_all<SF, 0, true, ADD, CT, false, SC, LT>(acc, Uk, Xc, co(s), o_fx, V, KS, invk, false, CKS);
+    hop_all<SF, 0, false, ADD, CT, false, SC, LT>(acc, Uk, Xc, co(n_bx), o_bx, V, KS, invk, false, CKS);
+    hop_all<SF, 1, true, ADD, CT, false, SC, LT>(acc, Uk, Xc, co(s), o_fy, V, KS, invk, false, CKS);
+    hop_all<SF, 1, false, ADD, CT, false, SC, LT>(acc, Uk, Xc, co(n_by), o_by, V, KS, invk, false, CKS);
+    hop_all<SF, 2, true, ADD, CT, false, SC, LT>(acc, Uk, Xc, co(s), o_fz, V, KS, invk, false, CKS);
+    hop_all<SF, 2, false, ADD, CT, false, SC, LT>(acc, Uk, Xc, co(n_bz), o_bz, V, KS, invk, false, CKS);
+    hop_all<SF, 3, true, ADD, CT, (NTP & 2) != 0, SC, LT>(acc, Uk, Xc, co(s), o_ft, V, KS, invk, neg_ft, CKS);
+    hop_all<SF, 3, false, ADD, CT, (NTP & 2) != 0, SC, LT>(acc, Uk, Xc, co(n_bt), o_bt, V, KS, invk, neg_bt, CKS);
     __builtin_amdgcn_sched_barrier(0);
 
     PY* Yc = Y + (size_t)c0 * cs;
@@ -320,7 +332,7 @@ __global__ void __launch_bounds__(256)
 #pragma unroll
         for (int chir = 0; chir < 2; ++chir) {
             Herm6<SC, R> T;
-            T.template load<(NTP & 1) != 0>(Cl, chir, co(s), V);
+            T.template load<(NTP & 1) != 0>(Cl, chir, cb(s), CKS);
 #pragma unroll
             for (int c = 0; c < CT; ++c) {
                 {
@@ -411,7 +423,7 @@ __global__ void __launch_bounds__(256)
     const int s = s0 >= 0 ? s0 : map_site(g, sm, blockIdx.x, 0);
     const size_t V = g.V;
     const size_t cs = 12 * V;         // column stride of a block vector
-    // the block-vector layout is a template argument here (VT = g.vt), so that the plane
+    // the block-vector layout is a template argument here (VT = g.vt & kVecTiled), so that the plane
     // stride of the tiled layout is a constant of the address arithmetic
     const size_t KS = VT ? (size_t)64 : V;  // plane stride of a block vector
     const auto vsite = [](int n) -> uint32_t { return VT ? (uint32_t)((n >> 6) * 768 + (n & 63)) : (uint32_t)n; };
@@ -434,14 +446,17 @@ __global__ void __launch_bounds__(256)
         // coefficient fields in storage SC: FP64, or FP32 / BF16 (two-row links, completed by
         // third_row, and 6x6 blocks, all widened to FP64 here, once per tile)
         constexpr uint32_t PC = sizeof(typename SC::P);
+        constexpr int NPL = kCompressedLinks<SC> ? 24 : 36;  // planes of the link field
+        const size_t CKS = coef_plane<PC>(g);
         const int sb = (w == 0) ? nb[1] : (w == 1) ? nb[3] : (w == 2) ? nb[5] : nb[7];
-        const uint32_t c_s = (uint32_t)s * PC, c_b = (uint32_t)sb * PC;
+        const uint32_t c_s = coef_site<PC>(g, s, NPL) * PC, c_b = coef_site<PC>(g, sb, NPL) * PC;
+        const uint32_t t_s = coef_site<PC>(g, s, 36) * PC;
         if constexpr (kCompressedLinks<SC>) {
             const bool neg_f = (w == 3) && bc_t && t == g.lt - 1, neg_b = (w == 3) && bc_t && t == 0;
             cx<double> uf[9], ub[9];
 #pragma unroll
             for (int k = 0; k < 6; ++k) {
-                const typename SC::P* pl = Uk + (size_t)(w * 6 + k) * V;
+                const typename SC::P* pl = Uk + (size_t)(w * 6 + k) * CKS;
                 const cx<typename SC::R> f = SC::ldb(pl, c_s), b = SC::ldb(pl, c_b);
                 uf[k] = {(double)f.re, (double)f.im};
                 ub[k] = {(double)b.re, (double)b.im};
@@ -456,7 +471,7 @@ __global__ void __launch_bounds__(256)
         } else {
 #pragma unroll
             for (int k = 0; k < 9; ++k) {
-                const typename SC::P* pl = Uk + (size_t)(w * 9 + k) * V;
+                const typename SC::P* pl = Uk + (size_t)(w * 9 + k) * CKS;
                 const cx<typename SC::R> f = SC::ldb(pl, c_s), b = SC::ldb(pl, c_b);
                 sU[(2 * w) * 9 + k][lane] = make_double2((double)f.re, (double)f.im);
                 sU[(2 * w + 1) * 9 + k][lane] = make_double2((double)b.re, (double)b.im);
@@ -466,7 +481,7 @@ __global__ void __launch_bounds__(256)
         // neighbour spinors and links other tiles reuse (measured 1-2 % faster)
 #pragma unroll
         for (int j = 0; j < 9; ++j) {
-            const cx<typename SC::R> v = SC::ldb_nt(Cl + (size_t)(w * 9 + j) * V, c_s);
+            const cx<typename SC::R> v = SC::ldb_nt(Cl + (size_t)(w * 9 + j) * CKS, t_s);
             sT[w * 9 + j][lane] = make_double2((double)v.re, (double)v.im);
         }
     }
@@ -641,17 +656,19 @@ __global__ void __launch_bounds__(256)
 #pragma unroll
     for (int d = 0; d < 8; ++d) on[d] = vec_site(g, nb[d]) * PB;
     const uint32_t o_s = vec_site(g, s) * PB;
-    const uint32_t c_s = (uint32_t)s * PB;  // the site in the coefficient fields
+    // the site in the coefficient fields (two-row links: 24 planes; blocks: 36)
+    const size_t CKS = coef_plane<PB>(g);
+    const uint32_t c_s = coef_site<PB>(g, s, 24) * PB, t_s = coef_site<PB>(g, s, 36) * PB;
     {
         // wave mu: the two stored rows of U_mu(x) and U_mu(x - mu), completed by third_row (the
         // antiperiodic sign of the time links on the last slice, seen from t = Lt - 1 forward and
         // from t = 0 backward), then stored in LDS as full 3 x 3 float matrices
-        const uint32_t ob = (uint32_t)((w == 0) ? nb[1] : (w == 1) ? nb[3] : (w == 2) ? nb[5] : nb[7]) * PB;
+        const uint32_t ob = coef_site<PB>(g, (w == 0) ? nb[1] : (w == 1) ? nb[3] : (w == 2) ? nb[5] : nb[7], 24) * PB;
         const bool neg_f = (w == 3) && bc_t && t == g.lt - 1, neg_b = (w == 3) && bc_t && t == 0;
         cx<R> uf[9], ub[9];
 #pragma unroll
         for (int k = 0; k < 6; ++k) {
-            const PF* pl = Uk + (size_t)(w * 6 + k) * V;
+            const PF* pl = Uk + (size_t)(w * 6 + k) * CKS;
             uf[k] = SF::ldb(pl, c_s);
             ub[k] = SF::ldb(pl, ob);
         }
@@ -664,7 +681,7 @@ __global__ void __launch_bounds__(256)
         }
 #pragma unroll
         for (int j = 0; j < 9; ++j) {
-            const cx<R> v = SF::ldb_nt(Cl + (size_t)(w * 9 + j) * V, c_s);
+            const cx<R> v = SF::ldb_nt(Cl + (size_t)(w * 9 + j) * CKS, t_s);
             sT[w * 9 + j][lane] = make_float2(v.re, v.im);
         }
     }
@@ -785,11 +802,13 @@ __global__ void __launch_bounds__(256)
     const uint32_t oF = vs * sizeof(typename SF::P);
     const uint32_t oI = vs * sizeof(typename SI::P);
     const uint32_t oY = vs * sizeof(typename SY::P);
-    const uint32_t oC = (uint32_t)s * sizeof(typename SC::P);
+    constexpr int PC = sizeof(typename SC::P);
+    const uint32_t oC = coef_site<PC>(g, s, 36) * PC;
+    const size_t CKS = coef_plane<PC>(g);
 #pragma unroll
     for (int chir = 0; chir < 2; ++chir) {
         Herm6<SC, R> T;
-        T.load(Cl, chir, oC, V);
+        T.load(Cl, chir, oC, CKS);
         for (int col = 0; col < L; ++col) {
             const typename SI::P* Rc = Rin + (size_t)col * cs;
             cx<R> v[6];
@@ -891,7 +910,7 @@ hipError_t launch_hop_t(const Geom& g, const LinkInfo& li, const void* Uk, const
             // a time; the sweep reads 18.2 instead of 20.1 GB in the same time)
             const SiteMap sm = make_site_map_rows(g, 12.0 * L * 16 + 72.0 * 16, MODE == APPLY ? 4 : 2);
             dim3 block(64, 4), grid(sm.nblk);
-            if (g.vt)
+            if (g.vt & kVecTiled)
                 k_hop_f64<MODE, 0, SC, 1><<<grid, block, 0, s>>>(
                     g, sm, (const typename SC::P*)Uk, (const typename SC::P*)Cl, (const double2*)X,
                     (const double2*)Rh, (double2*)Y, L, li.invk, li.bc_t);
@@ -960,11 +979,11 @@ hipError_t launch_sweep_td(const wd_ctx* c, const double2* X, const double2* R, 
     const bool pt = c->jacobi_kind == WD_JACOBI_POINT;
     const PC* U = (const PC*)c->f.Uk[pi];
     const PC* C = (const PC*)(pt ? c->f.Tp[pi] : c->f.Ti[pi]);
-    if (pt && c->g.vt)
+    if (pt && (c->g.vt & kVecTiled))
         k_hop_f64<JPOINT, FMT, SC, 1><<<grid, block, 0, s>>>(c->g, sm, U, C, X, R, Y, L, li.invk, li.bc_t);
     else if (pt)
         k_hop_f64<JPOINT, FMT, SC, 0><<<grid, block, 0, s>>>(c->g, sm, U, C, X, R, Y, L, li.invk, li.bc_t);
-    else if (c->g.vt)
+    else if (c->g.vt & kVecTiled)
         k_hop_f64<JBLOCK, FMT, SC, 1><<<grid, block, 0, s>>>(c->g, sm, U, C, X, R, Y, L, li.invk, li.bc_t);
     else
         k_hop_f64<JBLOCK, FMT, SC, 0><<<grid, block, 0, s>>>(c->g, sm, U, C, X, R, Y, L, li.invk, li.bc_t);
@@ -1030,7 +1049,8 @@ hipError_t jacobi_lowp(wd_ctx* c, int pi, const double2* R, double2* Z, int L, i
 }  // namespace
 
 hipError_t launch_apply_A(const wd_ctx* c, const double2* X, double2* Y, int L, hipStream_t s) {
-    return launch_hop_t<StF64, StF64, APPLY>(c->g, link_info(c), c->f.Uk[0], c->f.T, X, nullptr, Y, L, s);
+    // Tc[0]: T in the hop kernels' field layout (f.T keeps the standard one)
+    return launch_hop_t<StF64, StF64, APPLY>(c->g, link_info(c), c->f.Uk[0], c->f.Tc[0], X, nullptr, Y, L, s);
 }
 
 hipError_t launch_sweep_f64(const wd_ctx* c, const double2* X, const double2* R, double2* Y, int L, hipStream_t s) {

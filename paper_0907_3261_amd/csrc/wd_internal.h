@@ -175,8 +175,11 @@ struct Geom {
     int V;          // number of sites
     int sxy;        // lx*ly
     int sxyz;       // lx*ly*lz
-    int vt = 0;     // block vectors in the tiled layout (below); needs V % 64 == 0
+    // layout flags: bit 0 (kVecTiled) block vectors in the tiled layout (needs V % 64 == 0),
+    // bit 1 (kCoefTiled) the hop kernels' FP64 coefficient fields tiled (both below)
+    int vt = 0;
 };
+enum { kVecTiled = 1, kCoefTiled = 2 };
 
 // Device data layouts (all "pair" arrays, site index fastest):
 //   links      [mu][a*3+b][V]               4*9 pairs per site
@@ -196,11 +199,31 @@ __host__ __device__ constexpr int herm_index(int i, int j) {  // i < j, 6x6
 // Element offset of site s inside a column of a block vector (plane k adds k times
 // vec_plane), in the layout of g.
 __host__ __device__ __forceinline__ uint32_t vec_site(const Geom& g, int s) {
-    return g.vt ? (uint32_t)((s >> 6) * 768 + (s & 63)) : (uint32_t)s;
+    return (g.vt & kVecTiled) ? (uint32_t)((s >> 6) * 768 + (s & 63)) : (uint32_t)s;
 }
-__host__ __device__ __forceinline__ size_t vec_plane(const Geom& g) { return g.vt ? (size_t)64 : (size_t)g.V; }
+__host__ __device__ __forceinline__ size_t vec_plane(const Geom& g) {
+    return (g.vt & kVecTiled) ? (size_t)64 : (size_t)g.V;
+}
 // the tiled layout needs whole tiles and 32-bit byte offsets inside an FP64 column
 inline bool tiled_ok(const Geom& g) { return g.V % 64 == 0 && (long long)g.V * 192 <= 0xFFFFFFFFLL; }
+
+// The FP64 coefficient fields of the hop kernels (kappa-scaled links, T, T^{-1},
+// the point form; np planes of V pairs each) are kept tiled when the lattice
+// allows it: [V/64][np][64], so that a tile's links or 6x6 blocks are one
+// contiguous run (measured 1.5 % off the FP64 sweep and 1.4 % off A X at 32^3 x 64,
+// L = 12).  The FP32 and BF16 fields stay [np][V]: tiled, they gained nothing in the
+// LDS-staged kernels.  This is
+// private to the library (kCoefTiled, set by wd_set_params); 32-bit byte offsets over a
+// whole FP64 field of 36 planes need V <= 2^32 / 576.  PB: the field's pair size.
+inline bool coef_tiled_ok(const Geom& g) { return g.V % 64 == 0 && (long long)g.V * 576 <= 0xFFFFFFFFLL; }
+template <int PB>
+__host__ __device__ __forceinline__ uint32_t coef_site(const Geom& g, int s, int np) {
+    return (PB == 16 && (g.vt & kCoefTiled)) ? (uint32_t)((s >> 6) * np * 64 + (s & 63)) : (uint32_t)s;
+}
+template <int PB>
+__host__ __device__ __forceinline__ size_t coef_plane(const Geom& g) {
+    return (PB == 16 && (g.vt & kCoefTiled)) ? (size_t)64 : (size_t)g.V;
+}
 
 // Workgroup index -> tile index such that each of the 8 XCDs (which receive
 // workgroups round-robin) works on one contiguous range of tiles.
@@ -441,5 +464,8 @@ hipError_t launch_copy(double2* dst, const double2* src, size_t n, hipStream_t s
 hipError_t launch_zero(double2* dst, size_t n, hipStream_t s);
 // an L-column block vector from the standard into the tiled layout (to_tiled) or back
 hipError_t launch_retile(const double2* src, double2* dst, size_t V, int L, bool to_tiled, hipStream_t s);
+// a coefficient field of np planes of V pairs of pair_bytes (16, 8 or 4) from [np][V] into
+// [V/64][np][64]
+hipError_t launch_tile_field(const void* src, void* dst, size_t V, int np, int pair_bytes, hipStream_t s);
 
 }  // namespace wd

@@ -704,7 +704,7 @@ int wd_get_learned(wd_ctx* c, float* theta_host) {
 }
 
 int wd_learned_apply(wd_ctx* c, const void* R, void* Z, int L, int prec) {
-    if (c && c->g.vt) return WD_EINVAL;  // the learned kernels take the standard layout only
+    if (c && (c->g.vt & kVecTiled)) return WD_EINVAL;  // the learned kernels take the standard layout only
     if (!c || !R || !Z || L < 1 || L > c->max_L || (prec != WD_F64 && prec != WD_F32)) return WD_EINVAL;
     if (!c->have_links || !c->have_theta) return WD_ESTATE;
     const size_t bytes = (size_t)12 * c->g.V * L * 16;
@@ -721,7 +721,7 @@ int wd_learned_apply(wd_ctx* c, const void* R, void* Z, int L, int prec) {
 
 int wd_learned_train(wd_ctx* c, const void* Rp, const void* Ep, int n_pairs, int L, int steps, double lr,
                      int loss_kind, float* loss_hist) {
-    if (c && c->g.vt) return WD_EINVAL;  // the learned kernels take the standard layout only
+    if (c && (c->g.vt & kVecTiled)) return WD_EINVAL;  // the learned kernels take the standard layout only
     if (loss_kind != WD_LOSS_ERROR && loss_kind != WD_LOSS_RESIDUAL) return WD_EINVAL;
     if (!c || !Rp || (!Ep && loss_kind == WD_LOSS_ERROR) || L < 1 || L > c->max_L || n_pairs < L || steps < 0 ||
         !(lr > 0.0))
@@ -795,7 +795,7 @@ int wd_learned_train(wd_ctx* c, const void* Rp, const void* Ep, int n_pairs, int
 // Loss and gradient of the current theta on L pairs, without updating theta
 // (G: host buffer of 3 * 9 * 16 complex128, dl/dRe + i dl/dIm).
 int wd_learned_grad(wd_ctx* c, const void* R, const void* E, int L, int loss_kind, double* loss, double* G_host) {
-    if (c && c->g.vt) return WD_EINVAL;  // the learned kernels take the standard layout only
+    if (c && (c->g.vt & kVecTiled)) return WD_EINVAL;  // the learned kernels take the standard layout only
     if (loss_kind != WD_LOSS_ERROR && loss_kind != WD_LOSS_RESIDUAL) return WD_EINVAL;
     if (!c || !R || (!E && loss_kind == WD_LOSS_ERROR) || !loss || !G_host || L < 1 || L > c->max_L)
         return WD_EINVAL;
