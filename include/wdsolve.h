@@ -213,11 +213,9 @@ int wd_get_clover(wd_ctx* ctx, int which, double* out_host);
  * the lattice allows it: B and X are copied into the tiled layout when the solve
  * starts, X back when it ends and each snapshot (opts->x_snap) as it is taken
  * (two N x max_L blocks of device memory, allocated on first use; without them
- * the solve keeps the standard layout), except with the learned preconditioner.
- * The tiled layout needs V to be a multiple of 64 and at most 22369621 sites.
- * Under it wd_learned_apply, wd_learned_train, wd_learned_grad and solves with
- * the learned preconditioner return WD_EINVAL; wd_learned_pairs and every
- * other entry point follow the selected layout.
+ * the solve keeps the standard layout).  The tiled layout needs V to be a
+ * multiple of 64 and at most 22369621 sites; every entry point that takes block
+ * vectors, the learned preconditioner's included, follows the selected layout.
  * Errors: WD_EINVAL (unknown layout, lattice not divisible into tiles). */
 int wd_set_layout(wd_ctx* ctx, int layout);
 

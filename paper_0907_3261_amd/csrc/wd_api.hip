@@ -1028,7 +1028,6 @@ int solve_setup(wd_ctx* c, const void* Bv, void* Xv, int L, double tol, const wd
         return WD_EINVAL;
     if (op.precond == WD_PRECOND_LEARNED) {
         if (op.prec_inner == WD_BF16 || coef_prec(op.prec_inner)) return WD_EINVAL;
-        if (c->g.vt & kVecTiled) return WD_EINVAL;  // the learned kernels take the standard layout only
         if (!c->have_theta) return WD_ESTATE;
         int r0 = learned_ensure(c);
         if (r0) return r0;
@@ -1094,11 +1093,9 @@ int solve_common(wd_ctx* c, const void* Bv, void* Xv, int L, double tol, const w
     double2* X = (double2*)Xv;
     // A caller of the standard layout gets the solve in the tiled one (its stencils run
     // faster): B and X are copied into the tiled layout here, X back at the end and every
-    // snapshot as it is taken.  Not with the learned preconditioner, whose kernels take the
-    // standard layout only; without the two blocks of memory the solve stays in the standard
-    // layout.
-    const bool retile = !(c->g.vt & kVecTiled) && tiled_ok(c->g) && D.S.precond != WD_PRECOND_LEARNED &&
-                        tiled_ensure(c) == WD_OK;
+    // snapshot as it is taken; without the two blocks of memory the solve stays in the
+    // standard layout.
+    const bool retile = !(c->g.vt & kVecTiled) && tiled_ok(c->g) && tiled_ensure(c) == WD_OK;
     D.snap_untile = retile;
     rc = hipStreamSynchronize(c->stream) == hipSuccess ? WD_OK : WD_EHIP;
     if (rc == WD_OK && retile) {

@@ -22,14 +22,17 @@ namespace {
 
 constexpr int kNL = WD_LEARNED_LAYERS, kND = WD_LEARNED_DIRS;
 
-// S_d psi for one column at site s: returns 12 complex (index 3*spin + colour)
+// S_d psi for one column at site s: returns 12 complex (index 3*spin + colour).  V:
+// sites (the links' plane stride); KS, vs, vnb: the plane stride of the block vector
+// and the element offsets of s and nb in it (standard or tiled layout).
 template <class SZ>
 __device__ __forceinline__ void shifted(const float2* __restrict__ U, const typename SZ::P* __restrict__ Z, size_t V,
-                                        int d, int s, int nb, cx<float> (&q)[12]) {
+                                        size_t KS, int d, int s, int nb, uint32_t vs, uint32_t vnb,
+                                        cx<float> (&q)[12]) {
     if (d == 0) {
 #pragma unroll
         for (int k = 0; k < 12; ++k) {
-            const auto v = SZ::ld(Z, (size_t)k * V + s);
+            const auto v = SZ::ld(Z, (size_t)k * KS + vs);
             q[k] = {(float)v.re, (float)v.im};
         }
         return;
@@ -43,7 +46,7 @@ __device__ __forceinline__ void shifted(const float2* __restrict__ U, const type
     cx<float> p[12];
 #pragma unroll
     for (int k = 0; k < 12; ++k) {
-        const auto v = SZ::ld(Z, (size_t)k * V + nb);
+        const auto v = SZ::ld(Z, (size_t)k * KS + vnb);
         p[k] = {(float)v.re, (float)v.im};
     }
 #pragma unroll
@@ -80,10 +83,12 @@ struct Term {
 };
 
 // Issue the loads of a term.  KIND: 0 self term, 1 forward hop (link at the site),
-// 2 backward hop (daggered link at the neighbour).
+// 2 backward hop (daggered link at the neighbour).  vnb: element offset of the input
+// site in a plane of the block vector, KS its plane stride.
 template <int KIND, class SI, class SL, class R, int CT>
 __device__ __forceinline__ void term_load(Term<R, CT>& t, const typename SL::P* __restrict__ U, int mu, int ls,
-                                          const typename SI::P* __restrict__ Zin, size_t V, size_t col0, int nb) {
+                                          const typename SI::P* __restrict__ Zin, size_t V, size_t KS, size_t col0,
+                                          uint32_t vnb) {
     if (KIND != 0) {
 #pragma unroll
         for (int k = 0; k < 9; ++k) t.u[k] = SL::ld(U, (size_t)(mu * 9 + k) * V + ls);
@@ -93,7 +98,7 @@ __device__ __forceinline__ void term_load(Term<R, CT>& t, const typename SL::P* 
         const typename SI::P* zc = Zin + (col0 + c) * 12 * V;
 #pragma unroll
         for (int k = 0; k < 12; ++k) {
-            const auto v = SI::ld(zc, (size_t)k * V + nb);
+            const auto v = SI::ld(zc, (size_t)k * KS + vnb);
             t.p[c][k] = {(R)v.re, (R)v.im};
         }
     }
@@ -161,6 +166,8 @@ __global__ void __launch_bounds__(256) k_layer(const Geom g, const SiteMap sm, c
         return (co[mu] + 1 == ext[mu]) ? s - (ext[mu] - 1) * str[mu] : s + str[mu];
     };
     auto bwd_site = [&](int mu) { return (co[mu] == 0) ? s + (ext[mu] - 1) * str[mu] : s - str[mu]; };
+    const size_t KS = vec_plane(g);
+    const auto vo = [&](int n) { return vec_site(g, n); };
     cx<R> acc[CT][12];
 #pragma unroll
     for (int c = 0; c < CT; ++c)
@@ -169,28 +176,28 @@ __global__ void __launch_bounds__(256) k_layer(const Geom g, const SiteMap sm, c
     if constexpr (sizeof(R) == 4) {
         // FP32: two operand sets, the next term's loads in flight during the current term
         Term<R, CT> A, B;  // A: self and backward terms, B: forward terms
-        term_load<0, SI, SL>(A, U, 0, s, Zin, V, col0, s);
-        term_load<1, SI, SL>(B, U, 0, s, Zin, V, col0, fwd_site(0));
+        term_load<0, SI, SL>(A, U, 0, s, Zin, V, KS, col0, vo(s));
+        term_load<1, SI, SL>(B, U, 0, s, Zin, V, KS, col0, vo(fwd_site(0)));
         term_apply<0>(A, W, acc);
 #pragma unroll 1
         for (int mu = 0; mu < 4; ++mu) {
             const int bw = bwd_site(mu);
-            term_load<2, SI, SL>(A, U, mu, bw, Zin, V, col0, bw);
+            term_load<2, SI, SL>(A, U, mu, bw, Zin, V, KS, col0, vo(bw));
             term_apply<1>(B, W + (1 + 2 * mu) * 16, acc);
-            if (mu < 3) term_load<1, SI, SL>(B, U, mu + 1, s, Zin, V, col0, fwd_site(mu + 1));
+            if (mu < 3) term_load<1, SI, SL>(B, U, mu + 1, s, Zin, V, KS, col0, vo(fwd_site(mu + 1)));
             term_apply<2>(A, W + (2 + 2 * mu) * 16, acc);
         }
     } else {
         // FP64: one operand set (two would halve the occupancy)
         Term<R, CT> A;
-        term_load<0, SI, SL>(A, U, 0, s, Zin, V, col0, s);
+        term_load<0, SI, SL>(A, U, 0, s, Zin, V, KS, col0, vo(s));
         term_apply<0>(A, W, acc);
 #pragma unroll 1
         for (int mu = 0; mu < 4; ++mu) {
-            term_load<1, SI, SL>(A, U, mu, s, Zin, V, col0, fwd_site(mu));
+            term_load<1, SI, SL>(A, U, mu, s, Zin, V, KS, col0, vo(fwd_site(mu)));
             term_apply<1>(A, W + (1 + 2 * mu) * 16, acc);
             const int bw = bwd_site(mu);
-            term_load<2, SI, SL>(A, U, mu, bw, Zin, V, col0, bw);
+            term_load<2, SI, SL>(A, U, mu, bw, Zin, V, KS, col0, vo(bw));
             term_apply<2>(A, W + (2 + 2 * mu) * 16, acc);
         }
     }
@@ -199,7 +206,7 @@ __global__ void __launch_bounds__(256) k_layer(const Geom g, const SiteMap sm, c
         typename SO::P* oc = Zout + (col0 + c) * 12 * V;
 #pragma unroll
         for (int k = 0; k < 12; ++k)
-            SO::st(oc, (size_t)k * V + s,
+            SO::st(oc, (size_t)k * KS + vo(s),
                    cx<typename SO::R>{(typename SO::R)acc[c][k].re, (typename SO::R)acc[c][k].im});
     }
 }
@@ -224,7 +231,7 @@ __global__ void __launch_bounds__(kGB) k_wgrad(const Geom g, const float2* __res
                                                const typename SZ::P* __restrict__ Z, const float2* __restrict__ Gr,
                                                int d, double2* __restrict__ partial) {
     __shared__ double sh[kGB / 64][32];
-    const size_t V = g.V;
+    const size_t V = g.V, KS = vec_plane(g);
     const int col = blockIdx.y;
     const typename SZ::P* zc = Z + (size_t)col * 12 * V;
     const float2* gc = Gr + (size_t)col * 12 * V;
@@ -233,9 +240,11 @@ __global__ void __launch_bounds__(kGB) k_wgrad(const Geom g, const float2* __res
     for (int e = 0; e < 32; ++e) acc[e] = 0.0;
     for (int s = blockIdx.x * kGB + threadIdx.x; s < g.V; s += gridDim.x * kGB) {
         cx<float> q[12], gv[12];
-        shifted<SZ>(U, zc, V, d, s, neighbour(g, s, d), q);
+        const int nb = neighbour(g, s, d);
+        const uint32_t vs = vec_site(g, s);
+        shifted<SZ>(U, zc, V, KS, d, s, nb, vs, vec_site(g, nb), q);
 #pragma unroll
-        for (int k = 0; k < 12; ++k) gv[k] = StF32::ld(gc, (size_t)k * V + s);
+        for (int k = 0; k < 12; ++k) gv[k] = StF32::ld(gc, (size_t)k * KS + vs);
 #pragma unroll
         for (int sp = 0; sp < 4; ++sp)
 #pragma unroll
@@ -321,17 +330,19 @@ __global__ void __launch_bounds__(kGB) k_loss(const float2* __restrict__ Y, cons
 // Residual-space loss: with Ay = A M r (FP64) and r, per element d = Ay - r; the loss partials
 // sum |d|^2 / ||r||^2 per column, and out = gamma5 d / (||r||^2 L), the input of the second
 // application of A in dl/d(conj y) = gamma5 A gamma5 d / (||r||^2 L) (gamma5 negates the lower
-// spin pair, planes k = 6..11 of a column).  out may be Ay.
+// spin pair, planes k = 6..11 of a column).  out may be Ay.  tiled: the block vectors'
+// layout (the plane of element i follows from it).
 __global__ void __launch_bounds__(kGB) k_res_loss(const double2* Ay, const double2* __restrict__ R,
                                                   const double* __restrict__ rn2, size_t n_per_col, int L,
-                                                  double2* out, double* __restrict__ partial) {
+                                                  double2* out, double* __restrict__ partial, int tiled) {
     __shared__ double sh[kGB / 64];
     const size_t n = n_per_col * L;
     const size_t plane = n_per_col / 12;
     double acc = 0.0;
     for (size_t i = (size_t)blockIdx.x * kGB + threadIdx.x; i < n; i += (size_t)gridDim.x * kGB) {
         const int col = (int)(i / n_per_col);
-        const int k = (int)((i - (size_t)col * n_per_col) / plane);
+        const size_t row = i - (size_t)col * n_per_col;
+        const int k = tiled ? (int)((row % 768) / 64) : (int)(row / plane);
         const double inv = 1.0 / rn2[col];
         const double2 a = Ay[i], r = R[i];
         const double dr = a.x - r.x, di = a.y - r.y;
@@ -357,11 +368,11 @@ __global__ void k_to_f64(const float2* __restrict__ src, double2* __restrict__ d
     if (i < n) dst[i] = make_double2((double)src[i].x, (double)src[i].y);
 }
 __global__ void k_gamma5_to_f32(const double2* __restrict__ src, float2* __restrict__ dst, size_t n_per_col,
-                                size_t n) {
+                                size_t n, int tiled) {
     const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
-    const size_t plane = n_per_col / 12;
-    const int k = (int)((i % n_per_col) / plane);
+    const size_t plane = n_per_col / 12, r = i % n_per_col;
+    const int k = tiled ? (int)((r % 768) / 64) : (int)(r / plane);
     const double sg = k >= 6 ? -1.0 : 1.0;
     dst[i] = make_float2((float)(sg * src[i].x), (float)(sg * src[i].y));
 }
@@ -445,6 +456,7 @@ __global__ void __launch_bounds__(256) k_layer_lds(const Geom g, const SiteMap s
         int ln = lane;
         asm volatile("" : "+v"(ln));
         const typename SI::P* zc = Zin + (size_t)c * 12 * V;
+        const size_t KS = vec_plane(g);
         cx<R> acc[1][12];
 #pragma unroll
         for (int k = 0; k < 12; ++k) acc[0][k] = {R(0), R(0)};
@@ -452,7 +464,7 @@ __global__ void __launch_bounds__(256) k_layer_lds(const Geom g, const SiteMap s
         auto load_in = [&](Term<R, 1>& dst, int site) {
 #pragma unroll
             for (int k = 0; k < 12; ++k) {
-                const auto v = SI::ld(zc, (size_t)k * V + site);
+                const auto v = SI::ld(zc, (size_t)k * KS + vec_site(g, site));
                 dst.p[0][k] = {(R)v.re, (R)v.im};
             }
         };
@@ -480,7 +492,8 @@ __global__ void __launch_bounds__(256) k_layer_lds(const Geom g, const SiteMap s
         typename SO::P* oc = Zout + (size_t)c * 12 * V;
 #pragma unroll
         for (int k = 0; k < 12; ++k)
-            SO::st(oc, (size_t)k * V + s, cx<typename SO::R>{(typename SO::R)acc[0][k].re, (typename SO::R)acc[0][k].im});
+            SO::st(oc, (size_t)k * KS + vec_site(g, s),
+                   cx<typename SO::R>{(typename SO::R)acc[0][k].re, (typename SO::R)acc[0][k].im});
     }
 }
 
@@ -629,10 +642,10 @@ hipError_t batch_loss(wd_ctx* c, LearnWs& w, const double2* Rb, const double2* E
     if (e != hipSuccess) return e;
     k_to_f64<<<nblk(n, 256), 256, 0, s>>>(w.z[2], t1, n);
     if ((e = launch_apply_A(c, t1, t2, L, s)) != hipSuccess) return e;      // A y
-    k_res_loss<<<lblocks, kGB, 0, s>>>(t2, Rb, w.en2, ncol, L, t1, w.lpart);  // gamma5 (A y - r) / ...
+    k_res_loss<<<lblocks, kGB, 0, s>>>(t2, Rb, w.en2, ncol, L, t1, w.lpart, c->g.vt & kVecTiled);  // gamma5 (A y - r) / ...
     k_reduce_loss<<<1, kGB, 0, s>>>(w.lpart, lblocks, L, w.loss);
     if ((e = launch_apply_A(c, t1, t2, L, s)) != hipSuccess) return e;      // A gamma5 (A y - r)
-    k_gamma5_to_f32<<<nblk(n, 256), 256, 0, s>>>(t2, w.g[0], ncol, n);
+    k_gamma5_to_f32<<<nblk(n, 256), 256, 0, s>>>(t2, w.g[0], ncol, n, c->g.vt & kVecTiled);
     return hipGetLastError();
 }
 
@@ -704,7 +717,6 @@ int wd_get_learned(wd_ctx* c, float* theta_host) {
 }
 
 int wd_learned_apply(wd_ctx* c, const void* R, void* Z, int L, int prec) {
-    if (c && (c->g.vt & kVecTiled)) return WD_EINVAL;  // the learned kernels take the standard layout only
     if (!c || !R || !Z || L < 1 || L > c->max_L || (prec != WD_F64 && prec != WD_F32)) return WD_EINVAL;
     if (!c->have_links || !c->have_theta) return WD_ESTATE;
     const size_t bytes = (size_t)12 * c->g.V * L * 16;
@@ -721,7 +733,6 @@ int wd_learned_apply(wd_ctx* c, const void* R, void* Z, int L, int prec) {
 
 int wd_learned_train(wd_ctx* c, const void* Rp, const void* Ep, int n_pairs, int L, int steps, double lr,
                      int loss_kind, float* loss_hist) {
-    if (c && (c->g.vt & kVecTiled)) return WD_EINVAL;  // the learned kernels take the standard layout only
     if (loss_kind != WD_LOSS_ERROR && loss_kind != WD_LOSS_RESIDUAL) return WD_EINVAL;
     if (!c || !Rp || (!Ep && loss_kind == WD_LOSS_ERROR) || L < 1 || L > c->max_L || n_pairs < L || steps < 0 ||
         !(lr > 0.0))
@@ -749,7 +760,6 @@ int wd_learned_train(wd_ctx* c, const void* Rp, const void* Ep, int n_pairs, int
             if (!(en2[i] > 0.0) || !std::isfinite(en2[i])) return WD_EINVAL;
     }
     if (launch_zero(w.m, nparam, s) != hipSuccess || launch_zero(w.v, nparam, s) != hipSuccess) return WD_EHIP;
-    const unsigned lblocks = 1024;
     for (int step = 0; step < steps; ++step) {
         const int b = step % nbatch;
         const double2* Rb = (const double2*)Rp + (size_t)b * L * ncol;
@@ -795,7 +805,6 @@ int wd_learned_train(wd_ctx* c, const void* Rp, const void* Ep, int n_pairs, int
 // Loss and gradient of the current theta on L pairs, without updating theta
 // (G: host buffer of 3 * 9 * 16 complex128, dl/dRe + i dl/dIm).
 int wd_learned_grad(wd_ctx* c, const void* R, const void* E, int L, int loss_kind, double* loss, double* G_host) {
-    if (c && (c->g.vt & kVecTiled)) return WD_EINVAL;  // the learned kernels take the standard layout only
     if (loss_kind != WD_LOSS_ERROR && loss_kind != WD_LOSS_RESIDUAL) return WD_EINVAL;
     if (!c || !R || (!E && loss_kind == WD_LOSS_ERROR) || !loss || !G_host || L < 1 || L > c->max_L)
         return WD_EINVAL;
@@ -805,8 +814,6 @@ int wd_learned_grad(wd_ctx* c, const void* R, const void* E, int L, int loss_kin
     int r = learn_ws(c, w);
     if (r) return r;
     hipStream_t s = c->stream;
-    const size_t ncol = (size_t)12 * c->g.V;
-    const unsigned lblocks = 1024;
     const double2* Rb = (const double2*)R;
     const double2* Eb = (const double2*)E;
     if (launch_layer<StF64, StF32>(c, c->theta, Rb, w.z[0], L, s) != hipSuccess) return WD_EHIP;

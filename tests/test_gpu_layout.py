@@ -5,7 +5,8 @@ of k * V + s: the same matrices in another memory order.  Every kernel computes
 each site with the same arithmetic in the same order in either layout, so results
 must agree with the standard layout bit for bit, and with the FP64 oracle to the
 usual 1e-13.  The solver runs in the tiled layout for a caller of the standard one
-(copying B and X in and X out), which the bit-equal solve below checks as well.
+(copying B and X in and X out), which the bit-equal solve below checks as well; so
+do the learned preconditioner's layers, gradient and training.
 """
 
 import sys
@@ -196,23 +197,49 @@ def test_solve_in_tiled_context_equals_standard_caller(pkg):
     ct.close()
 
 
-def test_learned_entry_points_reject_tiled_layout(pkg):
-    dims = (4, 4, 4, 4)
+@pytest.mark.parametrize("L", [2, 3, 12])
+@pytest.mark.parametrize("prec", ["f64", "f32"])
+def test_learned_apply_tiled_equals_standard(pkg, L, prec):
+    """The learned layers (FP64: LDS-staged from three columns on; FP32: column tiles)."""
+    dims = (8, 16, 8, 3)
     U = wi.random_links(dims, 0.3, 217)
     c = _ctx(pkg, dims, U, 0.12, 1.0)
     c.learned_init("neumann")
-    R = _dev(wi.gaussian_block(256, 2, 218))
-    c.learned_apply(R, prec="f64")
+    V = wi.volume(dims)
+    R = wi.gaussian_block(V, L, 218)
+    Zs = _host(c.learned_apply(_dev(R), prec=prec))
     c.set_layout("tiled")
-    with pytest.raises(pkg.WDError):
-        c.learned_apply(R, prec="f64")
-    with pytest.raises(pkg.WDError):
-        c.learned_grad(R, R)
-    with pytest.raises(pkg.WDError):
-        c.solve(R, tol=1e-10, j=2, precond=pkg.WD_PRECOND_LEARNED)
-    c.set_layout("standard")
-    c.learned_apply(R, prec="f64")
+    Zt = untiled(_host(c.learned_apply(_dev(tiled(R)), prec=prec)))
+    assert np.array_equal(Zt, Zs)
     c.close()
+
+
+@pytest.mark.parametrize("loss", ["error", "residual"])
+def test_learned_gradient_and_training_tiled_equal_standard(pkg, loss):
+    """The weight gradient sums over sites in the same order in both layouts, so it agrees bit
+    for bit; the loss sums over elements in memory order and agrees to rounding; three Adam
+    steps then give the same weights."""
+    dims = (4, 4, 4, 8)
+    U = wi.random_links(dims, 0.3, 219)
+    V = wi.volume(dims)
+    R = wi.gaussian_block(V, 3, 220)
+    E = wi.gaussian_block(V, 3, 221)
+    Rp = wi.gaussian_block(V, 6, 222)
+    Ep = wi.gaussian_block(V, 6, 223)
+    res = {}
+    for layout in ("standard", "tiled"):
+        f = tiled if layout == "tiled" else (lambda b: b)
+        c = _ctx(pkg, dims, U, 0.12, 1.0)
+        c.set_layout(layout)
+        c.learned_init("neumann")
+        lv, G = c.learned_grad(_dev(f(R)), _dev(f(E)) if loss == "error" else None, loss=loss)
+        c.learned_train(_dev(f(Rp)), _dev(f(Ep)) if loss == "error" else None, L=3, steps=3, loss=loss)
+        res[layout] = (lv, G, c.get_learned())
+        c.close()
+    (ls_, Gs, ths), (lt, Gt, tht) = res["standard"], res["tiled"]
+    assert abs(lt - ls_) <= 1e-12 * abs(ls_)
+    assert np.array_equal(Gt, Gs)
+    assert np.array_equal(tht, ths)
 
 
 def test_full_size_jacobi_tiled_equals_standard(pkg):
