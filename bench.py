@@ -74,6 +74,9 @@ def parse():
     p.add_argument("--learned-c3", action="store_true",
                    help="only the learned-preconditioner workload at 16^3 x 32 (L = 12, ~2000 solver pairs, "
                         "vs Jacobi j = 12) at kappa 0.130 and 0.120")
+    p.add_argument("--hop-sweep", action="store_true",
+                   help="only the operator and Jacobi-sweep kernel timings against the block width L "
+                        "(1, 2, 3, 4, 6, 8, 12 up to the workload's L), in the layout the solver runs in")
     p.add_argument("--kernels-only", action="store_true",
                    help="only the hopping-kernel launches and a plain copy (for rocprofv3 counter runs)")
     return p.parse_args()
@@ -577,6 +580,26 @@ def main():
                                           "true_residual_max": float(np.max(info["true_residual"]))}
                 print(f"[bench] j-sweep kappa={kp} j={j}: {out[f'kappa{kp}_j{j}']}", file=sys.stderr, flush=True)
         print(json.dumps({"j_sweep": out, "workload": a.workload, "L": L}), flush=True)
+        ctx.close()
+        return
+    if a.hop_sweep:
+        # algorithmic GB/s of the two hop kernels per block width; per-application bytes below the
+        # 256 MB Infinity Cache are flagged (those inputs can stay cache-resident between launches)
+        out = {}
+        for l in (1, 2, 3, 4, 6, 8, 12):
+            if l > L:
+                continue
+            row = {}
+            for mode, name, per_site in ((0, "apply", 1152 + 384 * l), (1, "sweep", 1152 + 576 * l)):
+                ms = time_hop(ctx, torch, V, l, mode, a.hop_reps)
+                b = V * per_site
+                row[name] = {"ms": round(ms, 4), "GBs": round(b / (ms / 1e3) / 1e9, 1),
+                             "frac": round(b / (ms / 1e3) / 1e9 / HBM_PEAK_GBS, 4), "alg_bytes": b,
+                             "fits_in_mall": b <= 256e6}
+            out[f"L{l}"] = row
+            print(f"[bench] hop sweep L={l}: {row}", file=sys.stderr, flush=True)
+        print(json.dumps({"hop_sweep": out, "workload": a.workload,
+                          "layout": "tiled" if V % 64 == 0 else "standard"}), flush=True)
         ctx.close()
         return
     if a.ensembles > 0:
