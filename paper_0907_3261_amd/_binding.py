@@ -7,7 +7,8 @@ fallback path.
 Device memory is handled with PyTorch tensors (complex128 on a ROCm device):
 block vectors are tensors of shape (L, 12, V) -- column i, spin-colour
 k = 3*spin + colour, site s -- which is exactly the ABI's N x L column-major
-layout with row n = k*V + s.
+layout with row n = k*V + s.  After ``Context.set_layout("tiled")`` the same
+tensors hold the tiled row order n = (s//64)*768 + k*64 + s%64.
 """
 
 from __future__ import annotations
