@@ -515,8 +515,11 @@ __global__ void __launch_bounds__(256)
 #pragma unroll
             for (int k = 0; k < 12; ++k) acc[k] = StF64::ldb_nt(rc + (size_t)k * KS, o_s);
         }
-        // neighbour spinor of direction d (time-direction neighbours are streamed, as in k_hop);
-        // in the time-diagonal form the time hops load only the half they project onto
+        // neighbour spinor of direction d.  The sweeps stream the time-direction neighbours, as
+        // k_hop does; the operator, whose site map walks four t-slices together, loads them like
+        // the others (measured 1.8 % faster there, no gain in the sweeps).  In the time-diagonal
+        // form the time hops load only the half they project onto.
+        constexpr bool T_NT = MODE != APPLY;
         cx<double> p[2][12];
         auto load_dir = [&](cx<double>(&dst)[12], int d) {
             if (TD_IN && d >= 6) {
@@ -527,7 +530,7 @@ __global__ void __launch_bounds__(256)
             }
 #pragma unroll
             for (int k = 0; k < 12; ++k)
-                dst[k] = (d >= 6) ? StF64::ldb_nt(xc + (size_t)k * KS, on[d]) : StF64::ldb(xc + (size_t)k * KS, on[d]);
+                dst[k] = (T_NT && d >= 6) ? StF64::ldb_nt(xc + (size_t)k * KS, on[d]) : StF64::ldb(xc + (size_t)k * KS, on[d]);
         };
         load_dir(p[0], 0);
         static_for<0, 8>([&](auto dc) {
