@@ -505,7 +505,7 @@ hipError_t launch_layer_ct(const wd_ctx* c, const typename SL::P* U, const float
     if (ntile <= 0) return hipSuccess;
     const int ty = ntile < 4 ? ntile : 4;
     // XCD-aware site order in rows of the hop kernels' map, four t-slices walked together
-    // (fetched bytes 25-32 % below the plane-wide map at 32^3 x 64, L = 12)
+    // (a fifth to a third fewer fetched bytes than the plane-wide map at 32^3 x 64, L = 12)
     const SiteMap sm =
         make_site_map_rows(c->g, 12.0 * CT * ty * sizeof(typename SI::P) + 36.0 * sizeof(typename SL::P), 4);
     dim3 block(64, ty), grid(sm.nblk, (ntile + ty - 1) / ty);
